@@ -1,0 +1,236 @@
+/*
+ * chfsi.h -- C ABI of the MI355X R-ChFSI library.
+ *
+ * The library solves the finite-element generalized Hermitian eigenproblem
+ * H X = M X Lambda of noncollinear spin-orbit Kohn-Sham DFT (paper Sec.
+ * III-A): H is complex Hermitian of size 2M x 2M (M FE nodes, two spinor
+ * components), M is the real SPD FE mass matrix.  The solver is the
+ * residual-based Chebyshev filtered subspace iteration (R-ChFSI, Sec. III-B2,
+ * eq. rChFSIrecurrence and Algorithm RChFSI); its hot path is the
+ * matrix-free cell-level Hamiltonian-times-multivector product (Sec. III-C2,
+ * eq. cellHam, stages i-iv).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units       Hartree atomic units (Ha, bohr).
+ * Mesh        Periodic box of ncell[0] x ncell[1] x ncell[2] hexahedral cells
+ *             with edges h[d]; Lagrange elements of degree p on GLL nodes
+ *             (Sec. III-A), Gauss-Legendre quadrature with nq1d points per
+ *             direction (nq1d = p+1 integrates the kinetic and mass terms
+ *             exactly on these cells).  Cell e = ex + ncx*(ey + ncy*ez);
+ *             local node I = i + (p+1)*(j + (p+1)*k); quadrature point
+ *             q = a + nq1d*(b + nq1d*c) with ascending abscissae.  Global
+ *             node g = gx + Nx*(gy + Ny*gz), N_d = ncell[d]*p, gx = (ex*p+i)
+ *             mod Nx.  Every ncell[d] must be even (the cell colouring that
+ *             makes assembly race-free needs it) and p in 1..7.
+ * Vectors     A block of nvec spinor vectors is row-major complex
+ *             [M][2][ld] (interleaved re, im): row 2g+alpha holds spin alpha
+ *             of node g, the dof numbering of Sec. III-A; the vector index
+ *             is fastest, ld >= nvec.  Blocks are complex128 (double pairs)
+ *             in CHFSI_FP64 and complex64 (float pairs) in CHFSI_FP32 and
+ *             CHFSI_BF16.
+ * Fields      V[e][q] and B[e][q][3] (double, device memory): the local
+ *             potential and the magnetic field at the quadrature points.
+ * Precision   CHFSI_FP64: all products in double on FP64 MFMA.
+ *             CHFSI_FP32: cell GEMMs and projector products with float
+ *             operands on FP32 MFMA, float accumulation.
+ *             CHFSI_BF16: cell-GEMM operands rounded to bfloat16 (nearest
+ *             even), float accumulation on BF16 MFMA; pointwise and
+ *             projector terms in float.
+ *             The residual, the Chebyshev scalars, orthonormalization and
+ *             Rayleigh-Ritz always run in double (Sec. III-C2).
+ * Memory      The caller owns every device buffer.  chfsi_plan reports the
+ *             sizes of the two buffers the library needs (persistent tables
+ *             and scratch); the caller allocates them (e.g. with PyTorch)
+ *             and passes them to chfsi_setup.  Host arrays passed to
+ *             chfsi_setup are copied; the context keeps device pointers only.
+ *             The library itself calls no device allocator except inside
+ *             the BLAS handle it creates at setup.
+ * Streams     Every call is ordered on the given hipStream_t (NULL = the
+ *             null stream) and returns without waiting, unless stated.
+ * Errors      Functions return CHFSI_OK (0), a positive warning, or a
+ *             negative error code; they never throw.  chfsi_last_error(ctx)
+ *             (or (NULL) before a context exists) gives a message.  Argument
+ *             errors are detected before any device work is queued.
+ * Threads     A context may be used by one host thread at a time.  Calls
+ *             on one context that overlap on different streams race on the
+ *             scratch buffer.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct chfsi_ctx chfsi_ctx;
+
+enum {
+    CHFSI_OK = 0,
+    CHFSI_NOT_CONVERGED = 1,  /* chfsi_solve: max_iter reached; outputs valid */
+    CHFSI_E_ARG = -1,         /* invalid argument (message says which) */
+    CHFSI_E_DEVICE = -2,      /* a HIP or BLAS call failed */
+    CHFSI_E_NOT_SPD = -3,     /* Cholesky breakdown (rank-deficient block) */
+    CHFSI_E_BOUNDS = -4,      /* filter bounds not ordered lmin < lT < lmax */
+    CHFSI_E_NONFINITE = -5,   /* NaN or Inf in an input or a residual */
+    CHFSI_E_DIVERGED = -6,    /* residual grew by > 1e6 (bad lambda_max) */
+    CHFSI_E_WORKSPACE = -7,   /* a buffer is smaller than required */
+};
+
+typedef enum { CHFSI_FP64 = 0, CHFSI_FP32 = 1, CHFSI_BF16 = 2 } chfsi_prec;
+
+typedef struct {
+    int64_t ncell[3]; /* cells per direction, even, >= 2 */
+    double h[3];      /* cell edge lengths (bohr), > 0 */
+    int degree;       /* FE degree p, 1..7 */
+    int nq1d;         /* quadrature points per direction, 0 means p+1; <= 8 */
+} chfsi_mesh;
+
+/* Separable spin-orbit term H_nloc = sum_a P_a Delta_a P_a^H (Sec. II-A eq.
+ * hnloc; Sec. III-C2 item iv).  Projector beta_{a,j} (two-component,
+ * complex) is given by its samples at the quadrature points of every cell
+ * of its support; the library forms the cell projector matrices
+ * P_a(e)[I][alpha][j] = sum_q w_q |J| N_I(x_q) beta_{a,j,alpha}(x_q).
+ * All arrays are host memory, copied by chfsi_setup. */
+typedef struct {
+    int64_t natoms;            /* >= 0; 0 disables the term */
+    int nbeta;                 /* projectors per atom, 1..16 */
+    const int64_t *pair_ptr;   /* [natoms+1], CSR offsets of each atom's cells */
+    const int64_t *pair_cell;  /* [npairs], cells (each at most once per atom) */
+    const double *phi;         /* complex128 [npairs][nq][2][nbeta] */
+    const double *delta;       /* complex128 [natoms][nbeta][nbeta], Hermitian */
+} chfsi_projectors;
+
+/* Sizes of the caller-allocated buffers for blocks of up to max_nvec
+ * vectors.  persistent: operator tables (all precisions); scratch:
+ * temporaries of apply, filter (three recurrence blocks) and Rayleigh-Ritz.
+ * Both must be 256-byte aligned device memory. */
+int chfsi_plan(const chfsi_mesh *mesh, const chfsi_projectors *proj, int64_t max_nvec,
+               size_t *persistent_bytes, size_t *scratch_bytes);
+
+/* Builds the operator tables (Sec. III-A quadrature; Sec. III-C2 cell
+ * matrices) into `persistent` and returns a context.  V, B: device fields
+ * as above (copied into the tables; the caller may free them afterwards).
+ * proj may be NULL (no spin-orbit term).  Synchronizes `stream`. */
+int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B,
+                const chfsi_projectors *proj, int64_t max_nvec,
+                void *persistent, size_t persistent_bytes,
+                void *scratch, size_t scratch_bytes, void *stream, chfsi_ctx **out);
+
+/* Replaces the fields V, B (device) of an existing context (same mesh). */
+int chfsi_set_fields(chfsi_ctx *ctx, const double *V, const double *B, void *stream);
+
+/* Y = H X (Sec. III-C2: gather, cell contraction, spin-orbit projectors,
+ * colour-ordered assembly).  X, Y: device blocks of the precision's complex
+ * type; X and Y must not overlap.  1 <= nvec <= max_nvec, ld >= nvec. */
+int chfsi_apply_H(chfsi_ctx *ctx, chfsi_prec prec, const void *X, void *Y,
+                  int64_t nvec, int64_t ld, void *stream);
+
+/* Y = M X, the consistent mass matrix (Sec. III-A), complex128 blocks. */
+int chfsi_apply_M(chfsi_ctx *ctx, const void *X, void *Y, int64_t nvec, int64_t ld, void *stream);
+
+/* Adjoint of Y = H(V, B) X for the cotangent G (dL = Re sum conj(G) dY):
+ *   dX = H G (H is Hermitian),
+ *   dV[e][q]    = w_q|J| Re sum_{b,alpha} conj(g_{b,alpha}(x_q)) x_{b,alpha}(x_q),
+ *   dB[e][q][d] = w_q|J| Re sum_b g_b(x_q)^H sigma_d x_b(x_q),
+ * where x_b(x_q), g_b(x_q) are the fields interpolated to the quadrature
+ * points.  With G = X these are w|J| times the densities rho and m of Sec.
+ * II-A.  dX may be NULL; dV, dB (double, device) are overwritten. */
+int chfsi_apply_H_adjoint(chfsi_ctx *ctx, chfsi_prec prec, const void *X, const void *G,
+                          int64_t nvec, int64_t ld, void *dX, double *dV, double *dB, void *stream);
+
+/* Upper bound of the spectrum of D^{-1} H by a k-step Lanczos recurrence on
+ * D^{-1/2} H D^{-1/2} (the paper's estimate of the largest eigenvalue, Sec.
+ * IV-F): theta_max + |beta_k|.  v0: complex128 device vector [2M] (start
+ * vector, any nonzero).  Synchronizes; result in *lambda_max (host). */
+int chfsi_estimate_bounds(chfsi_ctx *ctx, int lanczos_steps, const void *v0,
+                          double *lambda_max, void *stream);
+
+/* R-ChFSI filter (eq. rChFSIrecurrence) of degree q >= 1 with bounds
+ * {lmin, lT, lmax} (host, lmin < lT < lmax):
+ *   Z_0 = 0, Z_1 = s1 R / e,
+ *   Z_{k+1} = (2 s_{k+1}/e)(H D^{-1} Z_k - c Z_k) - s_k s_{k+1} Z_{k-1}
+ *             + (2 s_{k+1}/e) R Lambda_k,
+ *   Y = D^{-1} Z_q + X Lambda_q,
+ * c = (lmax+lT)/2, e = (lmax-lT)/2, s1 = e/(lmin-c), s_{k+1} = 1/(2/s1-s_k),
+ * Lambda_k = C_k(diag(ritz)) by the same three-term rule.  The products
+ * H D^{-1} Z_k run in `prec` (Z stored in its complex type); X, R, Y are
+ * complex128 and R Lambda_k is formed in double.  ritz: double device [nvec].
+ * Y may alias X. */
+int chfsi_filter(chfsi_ctx *ctx, chfsi_prec prec, int degree, const double bounds[3],
+                 const void *X, const double *ritz, const void *R, void *Y,
+                 int64_t nvec, int64_t ld, void *stream);
+
+/* Cholesky-QR2 in the M inner product (the orthonormalization step of the
+ * Rayleigh-Ritz stage): two passes of S = Y^H MY, s = diag(S)^{-1/2},
+ * L L^H = diag(s) S diag(s), (Y, HY, MY) <- (.) diag(s) L^{-H}.  HY, MY:
+ * H Y and M Y on entry (MY required, HY may be NULL), updated in place.
+ * complex128 blocks.  Returns CHFSI_E_NOT_SPD on breakdown. */
+int chfsi_orthonormalize(chfsi_ctx *ctx, void *Y, void *HY, void *MY,
+                         int64_t nvec, int64_t ld, void *stream);
+
+/* Rayleigh-Ritz on an M-orthonormal block (Algorithm RChFSI, RR step):
+ * Hs = Y^H HY (Hermitian part), Hs Q = Q Lambda with ascending Lambda,
+ * Y <- Y Q, HY <- HY Q, MY <- MY Q.  ritz: double device [nvec] output.
+ * If R != NULL: R = HY - MY diag(ritz) and resnorm[j] = ||R_j||_2 (double
+ * device [nvec]; resnorm may be NULL). */
+int chfsi_rayleigh_ritz(chfsi_ctx *ctx, void *Y, void *HY, void *MY, int64_t nvec, int64_t ld,
+                        double *ritz, void *R, double *resnorm, void *stream);
+
+/* R = HX - MX diag(ritz) and resnorm[j] = ||R_j||_2 (complex128 blocks,
+ * double device vectors). */
+int chfsi_residual(chfsi_ctx *ctx, const void *HX, const void *MX, const double *ritz,
+                   void *R, double *resnorm, int64_t nvec, int64_t ld, void *stream);
+
+typedef struct {
+    chfsi_prec prec;    /* precision of the filter's products */
+    int degree;         /* Chebyshev degree q per iteration */
+    double tol;         /* stop when max_{j < n_wanted} ||R_j||_2 < tol */
+    int max_iter;       /* outer iterations (>= 1) */
+    int lanczos_steps;  /* steps of the lambda_max estimate (0: use lambda_max) */
+    double lambda_max;  /* used when lanczos_steps == 0 */
+    int fixed_iters;    /* if != 0, run exactly max_iter iterations (timing) */
+} chfsi_solve_opts;
+
+typedef struct {
+    int iters;              /* outer iterations done */
+    int converged;          /* 1 if the tolerance was met */
+    double max_res;         /* final max residual over the wanted columns */
+    double lambda_bounds[3];/* last lmin, lT, lmax */
+    double t_filter, t_rr, t_total; /* seconds (device events), summed */
+    double t_iter_median;   /* median seconds per iteration from the 2nd on */
+} chfsi_report;
+
+/* Workspace bytes chfsi_solve needs for nsub columns with leading dim ld. */
+int chfsi_solve_workspace(chfsi_ctx *ctx, int64_t nsub, int64_t ld, size_t *bytes);
+
+/* Algorithm RChFSI: from the start block X (complex128 [M][2][ld], nsub
+ * columns, overwritten with the Ritz vectors, M-orthonormal) and v0 for the
+ * Lanczos bound (complex128 [2M], may be NULL when lanczos_steps == 0):
+ * orthonormalize and Rayleigh-Ritz, then per iteration: residual (double),
+ * stop test, lmin = Lambda_1, lT = Lambda_nsub, filter in opts->prec,
+ * H Y and M Y in double, Cholesky-QR2, Rayleigh-Ritz.  eigvals: host
+ * [n_wanted] (ascending).  hist_res: optional host [max_iter+1] of the max
+ * wanted residual per iteration.  Synchronizes once per iteration.
+ * Returns CHFSI_OK, CHFSI_NOT_CONVERGED, or an error. */
+int chfsi_solve(chfsi_ctx *ctx, int64_t n_wanted, const chfsi_solve_opts *opts,
+                void *X, int64_t nsub, int64_t ld, const void *v0,
+                double *eigvals, double *hist_res, chfsi_report *report,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Mesh sizes of a context: nnodes (M), ncells, n (nodes per cell), nq. */
+int chfsi_info(const chfsi_ctx *ctx, int64_t *nnodes, int64_t *ncells, int *n, int *nq);
+
+/* The diagonal D (GLL-integrated mass, Sec. III-B2) as double device [M]. */
+int chfsi_mass_diag(chfsi_ctx *ctx, double *D, void *stream);
+
+const char *chfsi_last_error(const chfsi_ctx *ctx);
+void chfsi_destroy(chfsi_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHFSI_H */

@@ -1,0 +1,855 @@
+// C ABI of the R-ChFSI library: argument checking, operator tables, and the
+// host-side drivers of the filter (eq. rChFSIrecurrence), the Rayleigh-Ritz
+// stage and the eigensolver loop (Algorithm RChFSI).  Every arithmetic step
+// on vectors and subspace matrices runs in this library's kernels; the host
+// only carries scalars (Chebyshev coefficients, bounds, a 20x20 Lanczos
+// tridiagonal) and the control flow.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace chfsi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(chfsi_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t _e = (expr);                                                                    \
+        if (_e != hipSuccess)                                                                      \
+            return fail(ctx, CHFSI_E_DEVICE, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+    } while (0)
+
+#define BLASCHK(ctx, expr)                                                                         \
+    do {                                                                                           \
+        rocblas_status _s = (expr);                                                                \
+        if (_s != rocblas_status_success)                                                          \
+            return fail(ctx, CHFSI_E_DEVICE, std::string(#expr " failed: ") + rocblas_status_to_string(_s)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ----------------------------------------------------------------- 1D basis
+// Legendre polynomial P_n and its derivative (Bonnet recurrence).
+void legendre_eval(int n, double x, double &P, double &dP) {
+    if (n == 0) { P = 1; dP = 0; return; }
+    double pm = 1, pc = x, dm = 0, dc = 1;
+    for (int k = 1; k < n; ++k) {
+        double pn = ((2 * k + 1) * x * pc - k * pm) / (k + 1);
+        double dn = dm + (2 * k + 1) * pc;  // P'_{k+1} = P'_{k-1} + (2k+1) P_k
+        pm = pc; pc = pn; dm = dc; dc = dn;
+    }
+    P = pc;
+    dP = dc;
+}
+
+// Gauss-Legendre: roots of P_n (Newton from the Chebyshev-like guesses), ascending.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(n, 0); w.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(M_PI * (4.0 * (n - i) - 1.0) / (4.0 * n + 2.0));
+        for (int it = 0; it < 200; ++it) {
+            double P, dP;
+            legendre_eval(n, t, P, dP);
+            double d = P / dP;
+            t -= d;
+            if (std::fabs(d) < 4e-17) break;
+        }
+        double P, dP;
+        legendre_eval(n, t, P, dP);
+        x[i] = t;
+        w[i] = 2.0 / ((1 - t * t) * dP * dP);
+    }
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return x[a] < x[b]; });
+    std::vector<double> xs(n), ws(n);
+    for (int i = 0; i < n; ++i) { xs[i] = x[ord[i]]; ws[i] = w[ord[i]]; }
+    x = xs; w = ws;
+}
+
+// Gauss-Lobatto-Legendre: +-1 and the roots of P_{p-1} - P_{p+1} (which is
+// proportional to (1-x^2) P_p'), Newton; w_i = 2/(p(p+1) P_p(x_i)^2).
+void gauss_lobatto(int p, std::vector<double> &x, std::vector<double> &w) {
+    x.assign(p + 1, 0); w.assign(p + 1, 0);
+    x[0] = -1; x[p] = 1;
+    for (int i = 1; i < p; ++i) {
+        double t = -std::cos(M_PI * i / p);
+        for (int it = 0; it < 200; ++it) {
+            double Pa, dPa, Pb, dPb;
+            legendre_eval(p - 1, t, Pa, dPa);
+            legendre_eval(p + 1, t, Pb, dPb);
+            double d = (Pa - Pb) / (dPa - dPb);
+            t -= d;
+            if (std::fabs(d) < 4e-17) break;
+        }
+        x[i] = t;
+    }
+    for (int i = 0; i <= p; ++i) {
+        double P, dP;
+        legendre_eval(p, x[i], P, dP);
+        w[i] = 2.0 / (p * (p + 1.0) * P * P);
+    }
+}
+
+// Lagrange cardinal functions of `nodes` and their derivatives at t
+// (barycentric weights; derivative as the sum of the products leaving one
+// factor out).
+void cardinal(const std::vector<double> &nodes, double t, std::vector<double> &l, std::vector<double> &dl) {
+    const int n = (int)nodes.size();
+    l.assign(n, 0); dl.assign(n, 0);
+    for (int i = 0; i < n; ++i) {
+        double bw = 1;
+        for (int j = 0; j < n; ++j) if (j != i) bw /= (nodes[i] - nodes[j]);
+        double prod = 1;
+        for (int j = 0; j < n; ++j) if (j != i) prod *= (t - nodes[j]);
+        double d = 0;
+        for (int k = 0; k < n; ++k) {
+            if (k == i) continue;
+            double pk = 1;
+            for (int j = 0; j < n; ++j) if (j != i && j != k) pk *= (t - nodes[j]);
+            d += pk;
+        }
+        l[i] = bw * prod;
+        dl[i] = bw * d;
+    }
+}
+
+int pad_size(int need) {
+    static const int sizes[] = {32, 64, 128, 224, 352, 512};
+    for (int s : sizes) if (need <= s) return s;
+    return -1;
+}
+
+int build_mesh(const chfsi_mesh *mesh, const chfsi_projectors *proj, Mesh &m, std::string &msg) {
+    if (!mesh) { msg = "mesh is NULL"; return CHFSI_E_ARG; }
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->ncell[d] < 2 || (mesh->ncell[d] & 1)) {
+            msg = "ncell[" + std::to_string(d) + "] must be even and >= 2 (cell colouring)";
+            return CHFSI_E_ARG;
+        }
+        if (!(mesh->h[d] > 0) || !std::isfinite(mesh->h[d])) { msg = "h must be positive"; return CHFSI_E_ARG; }
+        m.ncell[d] = mesh->ncell[d];
+        m.h[d] = mesh->h[d];
+    }
+    if (mesh->degree < 1 || mesh->degree > 7) { msg = "degree must be in 1..7"; return CHFSI_E_ARG; }
+    m.p = mesh->degree;
+    m.n1 = m.p + 1;
+    m.n = m.n1 * m.n1 * m.n1;
+    m.nq1 = mesh->nq1d == 0 ? m.p + 1 : mesh->nq1d;
+    if (m.nq1 < 1 || m.nq1 > 8) { msg = "nq1d must be in 1..8"; return CHFSI_E_ARG; }
+    m.nq = m.nq1 * m.nq1 * m.nq1;
+    m.npad = pad_size(std::max(m.n, m.nq));
+    m.nqpad = m.npad;
+    m.ncells = m.ncell[0] * m.ncell[1] * m.ncell[2];
+    for (int d = 0; d < 3; ++d) m.Nd[d] = m.ncell[d] * m.p;
+    m.M = m.Nd[0] * m.Nd[1] * m.Nd[2];
+    if (m.ncells > (int64_t)1 << 30) { msg = "too many cells"; return CHFSI_E_ARG; }
+    m.natoms = 0; m.npairs = 0; m.nbeta = 0; m.n_nl_cells = 0;
+    if (proj && proj->natoms > 0) {
+        if (proj->nbeta < 1 || proj->nbeta > kMaxBeta) { msg = "nbeta must be in 1..16"; return CHFSI_E_ARG; }
+        if (!proj->pair_ptr || !proj->pair_cell || !proj->phi || !proj->delta) {
+            msg = "projector arrays must be non-NULL"; return CHFSI_E_ARG;
+        }
+        m.natoms = proj->natoms;
+        m.nbeta = proj->nbeta;
+        if (proj->pair_ptr[0] != 0) { msg = "pair_ptr[0] must be 0"; return CHFSI_E_ARG; }
+        for (int64_t a = 0; a < m.natoms; ++a)
+            if (proj->pair_ptr[a + 1] < proj->pair_ptr[a]) { msg = "pair_ptr not monotone"; return CHFSI_E_ARG; }
+        m.npairs = proj->pair_ptr[m.natoms];
+        if (m.npairs > (int64_t)1 << 30) { msg = "too many pairs"; return CHFSI_E_ARG; }
+        std::vector<char> has(m.ncells, 0);
+        for (int64_t pp = 0; pp < m.npairs; ++pp) {
+            int64_t e = proj->pair_cell[pp];
+            if (e < 0 || e >= m.ncells) { msg = "pair_cell out of range"; return CHFSI_E_ARG; }
+            has[e] = 1;
+        }
+        for (int64_t e = 0; e < m.ncells; ++e) m.n_nl_cells += has[e];
+    }
+    return CHFSI_OK;
+}
+
+Layout build_layout(const Mesh &m, int64_t max_nvec) {
+    Layout L{};
+    size_t o = 0;
+    const size_t NP2 = (size_t)m.npad * m.npad;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    L.K64 = take(NP2 * 8); L.Phi64 = take(NP2 * 8); L.PhiT64 = take(NP2 * 8); L.M64 = take(NP2 * 8);
+    L.K32 = take(NP2 * 4); L.Phi32 = take(NP2 * 4); L.PhiT32 = take(NP2 * 4);
+    L.Kb = take(NP2 * 2); L.Phib = take(NP2 * 2); L.PhiTb = take(NP2 * 2);
+    L.W64 = take((size_t)m.ncells * m.npad * 4 * 8);
+    L.W32 = take((size_t)m.ncells * m.npad * 4 * 4);
+    L.Wq = take((size_t)m.npad * 8);
+    L.D64 = take((size_t)m.M * 8);
+    L.Dinv64 = take((size_t)m.M * 8);
+    L.Dinv32 = take((size_t)m.M * 4);
+    L.colour_cells = take((size_t)m.ncells * 4);
+    L.nl_cells = take((size_t)std::max<int64_t>(m.n_nl_cells, 1) * 4);
+    L.cell_pair_ptr = take((size_t)(m.ncells + 1) * 4);
+    L.cell_pairs = take((size_t)std::max<int64_t>(m.npairs, 1) * 4);
+    L.pair_atom = take((size_t)std::max<int64_t>(m.npairs, 1) * 4);
+    L.atom_pair_ptr = take((size_t)(m.natoms + 1) * 4);
+    L.P64 = take((size_t)m.npairs * m.npad * 2 * m.nbeta * 16);
+    L.P32 = take((size_t)m.npairs * m.npad * 2 * m.nbeta * 8);
+    L.delta64 = take((size_t)m.natoms * m.nbeta * m.nbeta * 16);
+    L.persistent_bytes = o;
+
+    o = 0;
+    L.partial = take((size_t)m.npairs * m.nbeta * max_nvec * 16);
+    L.dcoef = take((size_t)m.natoms * m.nbeta * max_nvec * 16);
+    L.lamk = take((size_t)(kMaxDegree + 1) * max_nvec * 8);
+    L.small_bytes = (size_t)max_nvec * max_nvec * 16;
+    L.small = take(7 * L.small_bytes + 2 * (size_t)max_nvec * 8);
+    L.red_bytes = (size_t)256 * std::max<int64_t>(max_nvec, 2) * 8 + 4096 * 8;
+    L.red = take(L.red_bytes);
+    L.flag = take(256);
+    // filter: three recurrence blocks; Lanczos: four vectors and a table of M
+    L.Z = take(std::max<size_t>(3 * (size_t)(2 * m.M) * max_nvec * 16, 5 * (size_t)(2 * m.M) * 16));
+    size_t phi_bytes = (size_t)m.npairs * m.nq * 2 * m.nbeta * 16;
+    L.scratch_bytes = std::max(o, align256(L.Z + phi_bytes));
+    return L;
+}
+
+// tables of the reference cell (independent host implementation)
+struct HostTables {
+    std::vector<double> K, Phi, PhiT, Mref, wq, D;
+};
+
+void build_tables(const Mesh &m, HostTables &t) {
+    std::vector<double> xg, wg, xq, wqd;
+    gauss_lobatto(m.p, xg, wg);
+    gauss_legendre(m.nq1, xq, wqd);
+    const int n1 = m.n1, q1 = m.nq1, NP = m.npad;
+    std::vector<double> l1((size_t)q1 * n1), dl1((size_t)q1 * n1), l, dl;
+    for (int a = 0; a < q1; ++a) {
+        cardinal(xg, xq[a], l, dl);
+        for (int i = 0; i < n1; ++i) { l1[a * n1 + i] = l[i]; dl1[a * n1 + i] = dl[i]; }
+    }
+    std::vector<double> m1((size_t)n1 * n1, 0), k1((size_t)n1 * n1, 0);
+    for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j)
+            for (int a = 0; a < q1; ++a) {
+                m1[i * n1 + j] += wqd[a] * l1[a * n1 + i] * l1[a * n1 + j];
+                k1[i * n1 + j] += wqd[a] * dl1[a * n1 + i] * dl1[a * n1 + j];
+            }
+    const double detJ = m.h[0] * m.h[1] * m.h[2] / 8.0;
+    const double sx = 4.0 / (m.h[0] * m.h[0]), sy = 4.0 / (m.h[1] * m.h[1]), sz = 4.0 / (m.h[2] * m.h[2]);
+    t.K.assign((size_t)NP * NP, 0); t.Mref.assign((size_t)NP * NP, 0);
+    t.Phi.assign((size_t)NP * NP, 0); t.PhiT.assign((size_t)NP * NP, 0);
+    t.wq.assign(NP, 0);
+    for (int I = 0; I < m.n; ++I) {
+        int i = I % n1, j = (I / n1) % n1, k = I / (n1 * n1);
+        for (int J = 0; J < m.n; ++J) {
+            int ii = J % n1, jj = (J / n1) % n1, kk = J / (n1 * n1);
+            double mx = m1[i * n1 + ii], my = m1[j * n1 + jj], mz = m1[k * n1 + kk];
+            double kx = k1[i * n1 + ii], ky = k1[j * n1 + jj], kz = k1[k * n1 + kk];
+            t.K[(size_t)I * NP + J] = 0.5 * detJ * (sx * kx * my * mz + sy * mx * ky * mz + sz * mx * my * kz);
+            t.Mref[(size_t)I * NP + J] = detJ * mx * my * mz;
+        }
+    }
+    for (int q = 0; q < m.nq; ++q) {
+        int a = q % q1, b = (q / q1) % q1, c = q / (q1 * q1);
+        t.wq[q] = wqd[a] * wqd[b] * wqd[c] * detJ;
+        for (int I = 0; I < m.n; ++I) {
+            int i = I % n1, j = (I / n1) % n1, k = I / (n1 * n1);
+            double v = l1[a * n1 + i] * l1[b * n1 + j] * l1[c * n1 + k];
+            t.Phi[(size_t)q * NP + I] = v;
+            t.PhiT[(size_t)I * NP + q] = v;
+        }
+    }
+    t.D.assign(m.M, 0);
+    for (int64_t e = 0; e < m.ncells; ++e) {
+        int64_t ex = e % m.ncell[0], ey = (e / m.ncell[0]) % m.ncell[1], ez = e / (m.ncell[0] * m.ncell[1]);
+        for (int I = 0; I < m.n; ++I) {
+            int i = I % n1, j = (I / n1) % n1, k = I / (n1 * n1);
+            int64_t gx = (ex * m.p + i) % m.Nd[0], gy = (ey * m.p + j) % m.Nd[1], gz = (ez * m.p + k) % m.Nd[2];
+            t.D[gx + m.Nd[0] * (gy + m.Nd[1] * gz)] += detJ * wg[i] * wg[j] * wg[k];
+        }
+    }
+}
+
+// largest eigenvalue of the symmetric tridiagonal (alpha, beta[1..m-1]) by
+// Sturm-sequence bisection
+double tridiag_max(const std::vector<double> &al, const std::vector<double> &be) {
+    const int m = (int)al.size();
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+        double r = (i > 0 ? std::fabs(be[i]) : 0) + (i + 1 < m ? std::fabs(be[i + 1]) : 0);
+        lo = std::min(lo, al[i] - r);
+        hi = std::max(hi, al[i] + r);
+    }
+    auto count_below = [&](double x) {  // number of eigenvalues < x
+        int cnt = 0;
+        double d = 1;
+        for (int i = 0; i < m; ++i) {
+            double b2 = i > 0 ? be[i] * be[i] : 0;
+            d = al[i] - x - (i > 0 ? b2 / d : 0);
+            if (d == 0) d = -1e-300;
+            if (d < 0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= m) hi = mid; else lo = mid;
+        if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(hi))) break;
+    }
+    return hi;
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_block(chfsi_ctx *c, const void *p, int64_t nvec, int64_t ld, const char *name) {
+    if (!p) return fail(c, CHFSI_E_ARG, std::string(name) + " is NULL");
+    if (nvec < 1 || nvec > c->max_nvec)
+        return fail(c, CHFSI_E_ARG, "nvec must be in 1..max_nvec (" + std::to_string(c->max_nvec) + ")");
+    if (ld < nvec) return fail(c, CHFSI_E_ARG, "ld must be >= nvec");
+    return CHFSI_OK;
+}
+
+int read_flag(chfsi_ctx *c, hipStream_t s, int *out) {
+    int h = 0;
+    hipError_t e = hipMemcpyAsync(&h, c->S<int>(c->L.flag), sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(c, CHFSI_E_DEVICE, std::string("flag read failed: ") + hipGetErrorString(e));
+    *out = h;
+    return CHFSI_OK;
+}
+
+// S = A^H B (N x N row-major) for [rows][ld] blocks: column-major view of a
+// row-major block is its transpose, so S^T = Bcm * Acm^H in BLAS terms.
+int gram(chfsi_ctx *c, const cd *A, const cd *B, int64_t N, int64_t ld, cd *Sm, hipStream_t s) {
+    BLASCHK(c, rocblas_set_stream(c->blas, s));
+    const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
+    BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, (rocblas_int)N,
+                             (rocblas_int)N, (rocblas_int)(2 * c->m.M), &one,
+                             reinterpret_cast<const rocblas_double_complex *>(B), (rocblas_int)ld,
+                             reinterpret_cast<const rocblas_double_complex *>(A), (rocblas_int)ld, &zero,
+                             reinterpret_cast<rocblas_double_complex *>(Sm), (rocblas_int)N));
+    return CHFSI_OK;
+}
+
+// A <- A Q (A: [rows][ld] block with N columns; Q: N x N row-major), through
+// the compact temporary Z buffer and a strided copy back.
+int rotate(chfsi_ctx *c, cd *A, const cd *Q, int64_t N, int64_t ld, hipStream_t s) {
+    cd *tmp = c->S<cd>(c->L.Z);
+    const int64_t rows = 2 * c->m.M;
+    BLASCHK(c, rocblas_set_stream(c->blas, s));
+    const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
+    BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N,
+                             (rocblas_int)rows, (rocblas_int)N, &one,
+                             reinterpret_cast<const rocblas_double_complex *>(Q), (rocblas_int)N,
+                             reinterpret_cast<const rocblas_double_complex *>(A), (rocblas_int)ld, &zero,
+                             reinterpret_cast<rocblas_double_complex *>(tmp), (rocblas_int)N));
+    HIPCHK(c, hipMemcpy2DAsync(A, ld * sizeof(cd), tmp, N * sizeof(cd), N * sizeof(cd), rows,
+                               hipMemcpyDeviceToDevice, s));
+    return CHFSI_OK;
+}
+
+int apply_H_impl(chfsi_ctx *c, chfsi_prec prec, const void *X, void *Y, int64_t nvec, int64_t ld,
+                 hipStream_t s) {
+    const int nl = c->m.npairs > 0 ? FLAG_NLOC : 0;
+    if (nl) HIPCHK(c, launch_nonlocal_coeffs(c, prec, 0, X, nvec, ld, s));
+    HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, nl, 1.0, X, Y, nvec, ld, s));
+    return CHFSI_OK;
+}
+
+int orthonormalize_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, hipStream_t s) {
+    const Layout &L = c->L;
+    cd *Sm = c->S<cd>(L.small);
+    cd *T = Sm + L.small_bytes / sizeof(cd);
+    double *scale = reinterpret_cast<double *>(c->scr + L.small + 7 * L.small_bytes);
+    int *flag = c->S<int>(L.flag);
+    HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), s));
+    for (int pass = 0; pass < 2; ++pass) {
+        int rc = gram(c, Y, MY, nvec, ld, Sm, s);
+        if (rc) return rc;
+        HIPCHK(c, launch_herm_equilibrate((int)nvec, Sm, scale, flag, s));
+        HIPCHK(c, launch_cholesky((int)nvec, Sm, flag, s));
+        HIPCHK(c, launch_tri_inv_scale((int)nvec, Sm, scale, T, s));
+        int f = 0;
+        rc = read_flag(c, s, &f);
+        if (rc) return rc;
+        if (f) return fail(c, CHFSI_E_NOT_SPD, "Cholesky-QR breakdown: the block is (numerically) rank deficient");
+        if ((rc = rotate(c, Y, T, nvec, ld, s))) return rc;
+        if (HY && (rc = rotate(c, HY, T, nvec, ld, s))) return rc;
+        if ((rc = rotate(c, MY, T, nvec, ld, s))) return rc;
+    }
+    return CHFSI_OK;
+}
+
+int rr_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, double *ritz, cd *R,
+            double *resnorm, hipStream_t s) {
+    const Layout &L = c->L;
+    cd *Hs = c->S<cd>(L.small);
+    const size_t st = L.small_bytes / sizeof(cd);
+    cd *A2 = Hs + 2 * st, *V = Hs + 3 * st, *V2 = Hs + 4 * st;
+    int rc = gram(c, Y, HY, nvec, ld, Hs, s);
+    if (rc) return rc;
+    HIPCHK(c, launch_hermitize((int)nvec, Hs, s));
+    cd *Q = nullptr;
+    int sweeps = 0;
+    HIPCHK(c, launch_jacobi_eig((int)nvec, Hs, A2, V, V2, ritz, c->S<double>(L.red), 60, s, &sweeps, &Q));
+    if ((rc = rotate(c, Y, Q, nvec, ld, s))) return rc;
+    if ((rc = rotate(c, HY, Q, nvec, ld, s))) return rc;
+    if ((rc = rotate(c, MY, Q, nvec, ld, s))) return rc;
+    if (R || resnorm)
+        HIPCHK(c, launch_residual(2 * c->m.M, nvec, ld, HY, MY, ritz, R, c->S<double>(L.red), resnorm, s));
+    return CHFSI_OK;
+}
+
+int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds, const cd *X,
+                const double *ritz, const cd *R, cd *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+    const Layout &L = c->L;
+    const double lmin = bounds[0], lT = bounds[1], lmax = bounds[2];
+    const double cc = 0.5 * (lmax + lT), e = 0.5 * (lmax - lT);
+    const double s1 = e / (lmin - cc);
+    const bool z32 = prec != CHFSI_FP64;
+    const size_t zsz = z32 ? sizeof(cf) : sizeof(cd);
+    const int64_t rows = 2 * c->m.M;
+    char *zb = c->scr + L.Z;
+    const size_t zstride = align256((size_t)rows * nvec * zsz);
+    void *Zp = zb, *Zc = zb + zstride, *Zn = zb + 2 * zstride;
+    double *lamk = c->S<double>(L.lamk);
+    HIPCHK(c, launch_lamk_table(ritz, nvec, degree, cc, e, s1, lamk, nvec, s));
+    // Z_1 = s1 R / e
+    HIPCHK(c, launch_filter_init_ld(rows, nvec, nvec, ld, z32, Zc, nullptr, nullptr, R, 0, 0, nullptr, s1 / e, s));
+    double sk = s1;
+    const void *dinv = z32 ? (const void *)c->P<float>(L.Dinv32) : (const void *)c->P<double>(L.Dinv64);
+    (void)dinv;
+    const int nl = c->m.npairs > 0 ? FLAG_NLOC : 0;
+    for (int k = 1; k < degree; ++k) {
+        const double sn = 1.0 / (2.0 / s1 - sk);
+        const double a = 2.0 * sn / e;
+        // Z_{k+1} = -a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k
+        HIPCHK(c, launch_filter_init_ld(rows, nvec, nvec, ld, z32, Zn, Zc, k > 1 ? Zp : nullptr, R, -a * cc,
+                                        -sk * sn, lamk + (int64_t)k * nvec, a, s));
+        // Z_{k+1} += a H D^{-1} Z_k
+        if (nl) HIPCHK(c, launch_nonlocal_coeffs(c, prec, FLAG_DINV, Zc, nvec, nvec, s));
+        HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_ACCUM | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s));
+        void *t = Zp; Zp = Zc; Zc = Zn; Zn = t;
+        sk = sn;
+    }
+    HIPCHK(c, launch_recover_ld(rows, nvec, nvec, ld, z32, Zc, c->P<double>(L.Dinv64), X,
+                                lamk + (int64_t)degree * nvec, Y, s));
+    return CHFSI_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+int chfsi_plan(const chfsi_mesh *mesh, const chfsi_projectors *proj, int64_t max_nvec,
+               size_t *persistent_bytes, size_t *scratch_bytes) {
+    Mesh m{};
+    std::string msg;
+    int rc = build_mesh(mesh, proj, m, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    if (max_nvec < 1) return fail(nullptr, CHFSI_E_ARG, "max_nvec must be >= 1");
+    if (!persistent_bytes || !scratch_bytes) return fail(nullptr, CHFSI_E_ARG, "size outputs are NULL");
+    Layout L = build_layout(m, max_nvec);
+    *persistent_bytes = L.persistent_bytes;
+    *scratch_bytes = L.scratch_bytes;
+    return CHFSI_OK;
+}
+
+int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B, const chfsi_projectors *proj,
+                int64_t max_nvec, void *persistent, size_t persistent_bytes, void *scratch,
+                size_t scratch_bytes, void *stream, chfsi_ctx **out) {
+    if (!out) return fail(nullptr, CHFSI_E_ARG, "out is NULL");
+    *out = nullptr;
+    Mesh m{};
+    std::string msg;
+    int rc = build_mesh(mesh, proj, m, msg);
+    if (rc) return fail(nullptr, rc, msg);
+    if (max_nvec < 1) return fail(nullptr, CHFSI_E_ARG, "max_nvec must be >= 1");
+    if (!V || !B) return fail(nullptr, CHFSI_E_ARG, "V and B must be device pointers");
+    Layout L = build_layout(m, max_nvec);
+    if (!persistent || persistent_bytes < L.persistent_bytes)
+        return fail(nullptr, CHFSI_E_WORKSPACE, "persistent buffer too small: need " + std::to_string(L.persistent_bytes));
+    if (!scratch || scratch_bytes < L.scratch_bytes)
+        return fail(nullptr, CHFSI_E_WORKSPACE, "scratch buffer too small: need " + std::to_string(L.scratch_bytes));
+    if ((reinterpret_cast<uintptr_t>(persistent) & 255) || (reinterpret_cast<uintptr_t>(scratch) & 255))
+        return fail(nullptr, CHFSI_E_ARG, "buffers must be 256-byte aligned");
+
+    chfsi_ctx *c = new (std::nothrow) chfsi_ctx();
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "out of host memory");
+    c->m = m;
+    c->L = L;
+    c->max_nvec = max_nvec;
+    c->pers = static_cast<char *>(persistent);
+    c->scr = static_cast<char *>(scratch);
+    c->blas = nullptr;
+    hipStream_t s = S(stream);
+
+    HostTables t;
+    build_tables(m, t);
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        return hipMemcpyAsync(c->pers + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    const size_t NP2 = (size_t)m.npad * m.npad;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(L.K64, t.K.data(), NP2 * 8);
+    if (e == hipSuccess) e = up(L.Phi64, t.Phi.data(), NP2 * 8);
+    if (e == hipSuccess) e = up(L.PhiT64, t.PhiT.data(), NP2 * 8);
+    if (e == hipSuccess) e = up(L.M64, t.Mref.data(), NP2 * 8);
+    if (e == hipSuccess) e = up(L.Wq, t.wq.data(), m.npad * 8);
+    if (e == hipSuccess) e = up(L.D64, t.D.data(), m.M * 8);
+    // colour classes: cells of equal coordinate parity share no node
+    std::vector<int> cells;
+    cells.reserve(m.ncells);
+    for (int col = 0; col < 8; ++col) {
+        c->colour_ptr[col] = (int64_t)cells.size();
+        for (int64_t ez = (col >> 2) & 1; ez < m.ncell[2]; ez += 2)
+            for (int64_t ey = (col >> 1) & 1; ey < m.ncell[1]; ey += 2)
+                for (int64_t ex = col & 1; ex < m.ncell[0]; ex += 2)
+                    cells.push_back((int)(ex + m.ncell[0] * (ey + m.ncell[1] * ez)));
+    }
+    c->colour_ptr[8] = (int64_t)cells.size();
+    std::vector<int> cpp(m.ncells + 1, 0), cps(std::max<int64_t>(m.npairs, 1), 0),
+        patom(std::max<int64_t>(m.npairs, 1), 0), app(m.natoms + 1, 0), nlc;
+    if (m.npairs > 0) {
+        for (int64_t a = 0; a < m.natoms; ++a) {
+            app[a + 1] = (int)proj->pair_ptr[a + 1];
+            for (int64_t pp = proj->pair_ptr[a]; pp < proj->pair_ptr[a + 1]; ++pp) {
+                patom[pp] = (int)a;
+                cpp[proj->pair_cell[pp] + 1]++;
+            }
+        }
+        for (int64_t e2 = 0; e2 < m.ncells; ++e2) cpp[e2 + 1] += cpp[e2];
+        std::vector<int> fill(cpp.begin(), cpp.end() - 1);
+        for (int64_t pp = 0; pp < m.npairs; ++pp) cps[fill[proj->pair_cell[pp]]++] = (int)pp;
+        for (int64_t e2 = 0; e2 < m.ncells; ++e2)
+            if (cpp[e2 + 1] > cpp[e2]) nlc.push_back((int)e2);
+    }
+    if (nlc.empty()) nlc.push_back(0);
+    if (e == hipSuccess) e = up(L.colour_cells, cells.data(), cells.size() * 4);
+    if (e == hipSuccess) e = up(L.cell_pair_ptr, cpp.data(), cpp.size() * 4);
+    if (e == hipSuccess) e = up(L.cell_pairs, cps.data(), cps.size() * 4);
+    if (e == hipSuccess) e = up(L.pair_atom, patom.data(), patom.size() * 4);
+    if (e == hipSuccess) e = up(L.atom_pair_ptr, app.data(), app.size() * 4);
+    if (e == hipSuccess) e = up(L.nl_cells, nlc.data(), nlc.size() * 4);
+    if (e == hipSuccess && m.natoms > 0)
+        e = up(L.delta64, proj->delta, (size_t)m.natoms * m.nbeta * m.nbeta * 16);
+    if (e == hipSuccess && m.npairs > 0)
+        e = hipMemcpyAsync(c->scr + L.Z, proj->phi, (size_t)m.npairs * m.nq * 2 * m.nbeta * 16,
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_setup_casts(c, s);
+    if (e == hipSuccess) e = launch_setup_fields(c, V, B, s);
+    if (e == hipSuccess) e = launch_setup_projectors(c, reinterpret_cast<const cd *>(c->scr + L.Z), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        std::string em = std::string("setup failed: ") + hipGetErrorString(e);
+        delete c;
+        return fail(nullptr, CHFSI_E_DEVICE, em);
+    }
+    if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
+        delete c;
+        return fail(nullptr, CHFSI_E_DEVICE, "rocblas_create_handle failed");
+    }
+    *out = c;
+    return CHFSI_OK;
+}
+
+int chfsi_set_fields(chfsi_ctx *c, const double *V, const double *B, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (!V || !B) return fail(c, CHFSI_E_ARG, "V and B must be device pointers");
+    hipStream_t s = S(stream);
+    int *flag = c->S<int>(c->L.flag);
+    HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), s));
+    HIPCHK(c, launch_check_finite(V, c->m.ncells * c->m.nq, flag, s));
+    HIPCHK(c, launch_check_finite(B, c->m.ncells * c->m.nq * 3, flag, s));
+    int f = 0;
+    int rc = read_flag(c, s, &f);
+    if (rc) return rc;
+    if (f) return fail(c, CHFSI_E_NONFINITE, "V or B holds NaN or Inf");
+    HIPCHK(c, launch_setup_fields(c, V, B, s));
+    return CHFSI_OK;
+}
+
+int chfsi_apply_H(chfsi_ctx *c, chfsi_prec prec, const void *X, void *Y, int64_t nvec, int64_t ld, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (prec < CHFSI_FP64 || prec > CHFSI_BF16) return fail(c, CHFSI_E_ARG, "unknown precision");
+    int rc;
+    if ((rc = check_block(c, X, nvec, ld, "X")) || (rc = check_block(c, Y, nvec, ld, "Y"))) return rc;
+    if (X == Y) return fail(c, CHFSI_E_ARG, "X and Y must not overlap");
+    return apply_H_impl(c, prec, X, Y, nvec, ld, S(stream));
+}
+
+int chfsi_apply_M(chfsi_ctx *c, const void *X, void *Y, int64_t nvec, int64_t ld, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_block(c, X, nvec, ld, "X")) || (rc = check_block(c, Y, nvec, ld, "Y"))) return rc;
+    if (X == Y) return fail(c, CHFSI_E_ARG, "X and Y must not overlap");
+    HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, Y, nvec, ld, S(stream)));
+    return CHFSI_OK;
+}
+
+int chfsi_apply_H_adjoint(chfsi_ctx *c, chfsi_prec prec, const void *X, const void *G, int64_t nvec, int64_t ld,
+                          void *dX, double *dV, double *dB, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (prec < CHFSI_FP64 || prec > CHFSI_BF16) return fail(c, CHFSI_E_ARG, "unknown precision");
+    int rc;
+    if ((rc = check_block(c, X, nvec, ld, "X")) || (rc = check_block(c, G, nvec, ld, "G"))) return rc;
+    if (!dV || !dB) return fail(c, CHFSI_E_ARG, "dV and dB must be device pointers");
+    hipStream_t s = S(stream);
+    if (dX) {
+        if (dX == G || dX == X) return fail(c, CHFSI_E_ARG, "dX must not overlap X or G");
+        if ((rc = apply_H_impl(c, prec, G, dX, nvec, ld, s))) return rc;
+    }
+    HIPCHK(c, launch_adjoint_fields(c, prec, X, G, nvec, ld, dV, dB, s));
+    return CHFSI_OK;
+}
+
+int chfsi_estimate_bounds(chfsi_ctx *c, int steps, const void *v0, double *lambda_max, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (!v0 || !lambda_max) return fail(c, CHFSI_E_ARG, "v0 and lambda_max must be non-NULL");
+    if (steps < 1 || steps > 1000) return fail(c, CHFSI_E_ARG, "lanczos_steps must be in 1..1000");
+    hipStream_t s = S(stream);
+    const int64_t N = 2 * c->m.M;
+    cd *v = c->S<cd>(c->L.Z), *vp = v + N, *w = vp + N, *t = w + N;
+    double *red = c->S<double>(c->L.red), *dsc = red + 4000;
+    double h = 0;
+    auto dot = [&](const cd *a, const cd *b, double &res) -> int {
+        HIPCHK(c, launch_dot_real(N, a, b, red, dsc, s));
+        HIPCHK(c, hipMemcpyAsync(&res, dsc, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return CHFSI_OK;
+    };
+    HIPCHK(c, hipMemcpyAsync(v, v0, N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemsetAsync(vp, 0, N * sizeof(cd), s));
+    int rc = dot(v, v, h);
+    if (rc) return rc;
+    if (!(h > 0) || !std::isfinite(h)) return fail(c, CHFSI_E_ARG, "v0 must be a nonzero finite vector");
+    HIPCHK(c, launch_axpby(N, 0.0, nullptr, 1.0 / std::sqrt(h), v, s));
+    std::vector<double> al, be(1, 0.0);
+    // D^{-1/2} as a length-M table in the reduction area of the Lanczos vectors
+    double *dh = reinterpret_cast<double *>(t + N);
+    std::vector<double> Dh(c->m.M);
+    HIPCHK(c, hipMemcpyAsync(Dh.data(), c->P<double>(c->L.Dinv64), c->m.M * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (auto &x : Dh) x = std::sqrt(x);
+    HIPCHK(c, hipMemcpyAsync(dh, Dh.data(), c->m.M * 8, hipMemcpyHostToDevice, s));
+    for (int j = 0; j < steps; ++j) {
+        HIPCHK(c, hipMemcpyAsync(t, v, N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, launch_scale_rows(N, 1, 1, dh, t, s));
+        if ((rc = apply_H_impl(c, CHFSI_FP64, t, w, 1, 1, s))) return rc;
+        HIPCHK(c, launch_scale_rows(N, 1, 1, dh, w, s));
+        HIPCHK(c, launch_axpby(N, -be[j], vp, 1.0, w, s));
+        double a;
+        if ((rc = dot(v, w, a))) return rc;
+        al.push_back(a);
+        HIPCHK(c, launch_axpby(N, -a, v, 1.0, w, s));
+        double b2;
+        if ((rc = dot(w, w, b2))) return rc;
+        double b = std::sqrt(std::max(b2, 0.0));
+        be.push_back(b);
+        if (b == 0 || !std::isfinite(b)) break;
+        HIPCHK(c, hipMemcpyAsync(vp, v, N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(v, w, N * sizeof(cd), hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, launch_axpby(N, 0.0, nullptr, 1.0 / b, v, s));
+    }
+    if (!std::isfinite(be.back())) return fail(c, CHFSI_E_NONFINITE, "Lanczos produced a non-finite value");
+    std::vector<double> bt(be.begin(), be.begin() + al.size());
+    *lambda_max = tridiag_max(al, bt) + std::fabs(be[al.size()]);
+    return CHFSI_OK;
+}
+
+int chfsi_filter(chfsi_ctx *c, chfsi_prec prec, int degree, const double bounds[3], const void *X,
+                 const double *ritz, const void *R, void *Y, int64_t nvec, int64_t ld, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (prec < CHFSI_FP64 || prec > CHFSI_BF16) return fail(c, CHFSI_E_ARG, "unknown precision");
+    if (degree < 1 || degree > kMaxDegree) return fail(c, CHFSI_E_ARG, "degree must be in 1..256");
+    if (!bounds || !ritz) return fail(c, CHFSI_E_ARG, "bounds and ritz must be non-NULL");
+    int rc;
+    if ((rc = check_block(c, X, nvec, ld, "X")) || (rc = check_block(c, R, nvec, ld, "R")) ||
+        (rc = check_block(c, Y, nvec, ld, "Y")))
+        return rc;
+    if (!(bounds[0] < bounds[1] && bounds[1] < bounds[2]) || !std::isfinite(bounds[0]) || !std::isfinite(bounds[2]))
+        return fail(c, CHFSI_E_BOUNDS, "bounds must satisfy lmin < lT < lmax");
+    if (R == Y) return fail(c, CHFSI_E_ARG, "Y must not overlap R");
+    return filter_impl(c, prec, degree, bounds, (const cd *)X, ritz, (const cd *)R, (cd *)Y, nvec, ld, S(stream));
+}
+
+int chfsi_orthonormalize(chfsi_ctx *c, void *Y, void *HY, void *MY, int64_t nvec, int64_t ld, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_block(c, Y, nvec, ld, "Y")) || (rc = check_block(c, MY, nvec, ld, "MY"))) return rc;
+    return orthonormalize_impl(c, (cd *)Y, (cd *)HY, (cd *)MY, nvec, ld, S(stream));
+}
+
+int chfsi_rayleigh_ritz(chfsi_ctx *c, void *Y, void *HY, void *MY, int64_t nvec, int64_t ld, double *ritz,
+                        void *R, double *resnorm, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_block(c, Y, nvec, ld, "Y")) || (rc = check_block(c, HY, nvec, ld, "HY")) ||
+        (rc = check_block(c, MY, nvec, ld, "MY")))
+        return rc;
+    if (!ritz) return fail(c, CHFSI_E_ARG, "ritz is NULL");
+    return rr_impl(c, (cd *)Y, (cd *)HY, (cd *)MY, nvec, ld, ritz, (cd *)R, resnorm, S(stream));
+}
+
+int chfsi_residual(chfsi_ctx *c, const void *HX, const void *MX, const double *ritz, void *R, double *resnorm,
+                   int64_t nvec, int64_t ld, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_block(c, HX, nvec, ld, "HX")) || (rc = check_block(c, MX, nvec, ld, "MX"))) return rc;
+    if (!ritz) return fail(c, CHFSI_E_ARG, "ritz is NULL");
+    HIPCHK(c, launch_residual(2 * c->m.M, nvec, ld, (const cd *)HX, (const cd *)MX, ritz, (cd *)R,
+                              c->S<double>(c->L.red), resnorm, S(stream)));
+    return CHFSI_OK;
+}
+
+int chfsi_solve_workspace(chfsi_ctx *c, int64_t nsub, int64_t ld, size_t *bytes) {
+    if (!c || !bytes) return fail(c, CHFSI_E_ARG, "ctx and bytes must be non-NULL");
+    if (nsub < 1 || nsub > c->max_nvec || ld < nsub) return fail(c, CHFSI_E_ARG, "bad nsub or ld");
+    const size_t blk = align256((size_t)(2 * c->m.M) * ld * sizeof(cd));
+    *bytes = 3 * blk + align256((size_t)nsub * 8 * 2);
+    return CHFSI_OK;
+}
+
+int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void *Xv, int64_t nsub, int64_t ld,
+                const void *v0, double *eigvals, double *hist_res, chfsi_report *rep, void *workspace,
+                size_t workspace_bytes, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (!o) return fail(c, CHFSI_E_ARG, "opts is NULL");
+    int rc;
+    if ((rc = check_block(c, Xv, nsub, ld, "X"))) return rc;
+    if (n_wanted < 1 || n_wanted > nsub) return fail(c, CHFSI_E_ARG, "n_wanted must be in 1..nsub");
+    if (nsub < 2) return fail(c, CHFSI_E_ARG, "nsub must be >= 2");
+    if (o->degree < 1 || o->degree > kMaxDegree || o->max_iter < 1) return fail(c, CHFSI_E_ARG, "bad degree or max_iter");
+    if (o->prec < CHFSI_FP64 || o->prec > CHFSI_BF16) return fail(c, CHFSI_E_ARG, "unknown precision");
+    if (!eigvals) return fail(c, CHFSI_E_ARG, "eigvals is NULL");
+    size_t need = 0;
+    if ((rc = chfsi_solve_workspace(c, nsub, ld, &need))) return rc;
+    if (!workspace || workspace_bytes < need) return fail(c, CHFSI_E_WORKSPACE, "workspace too small: need " + std::to_string(need));
+    hipStream_t s = S(stream);
+    const size_t blk = align256((size_t)(2 * c->m.M) * ld * sizeof(cd));
+    char *ws = static_cast<char *>(workspace);
+    cd *X = (cd *)Xv, *HX = (cd *)ws, *MX = (cd *)(ws + blk), *R = (cd *)(ws + 2 * blk);
+    double *ritz = (double *)(ws + 3 * blk), *res = ritz + nsub;
+    double lmax = o->lambda_max;
+    if (o->lanczos_steps > 0) {
+        if (!v0) return fail(c, CHFSI_E_ARG, "v0 is NULL but lanczos_steps > 0");
+        if ((rc = chfsi_estimate_bounds(c, o->lanczos_steps, v0, &lmax, stream))) return rc;
+    }
+    if (!(std::isfinite(lmax))) return fail(c, CHFSI_E_BOUNDS, "lambda_max is not finite");
+    hipEvent_t ev[4];
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    auto cleanup = [&]() { for (auto &e : ev) hipEventDestroy(e); };
+    HIPCHK(c, hipEventRecord(ev[0], s));
+    if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { cleanup(); return rc; }
+    HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
+    if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { cleanup(); return rc; }
+    if ((rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s))) { cleanup(); return rc; }
+    std::vector<double> hr(nsub), hritz(nsub), titer;
+    double t_filter = 0, t_rr = 0, first_res = -1;
+    int it = 0, converged = 0;
+    double maxres = 0, bounds[3] = {0, 0, lmax};
+    int status = CHFSI_OK;
+    for (;; ++it) {
+        HIPCHK(c, hipMemcpyAsync(hr.data(), res, nsub * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(hritz.data(), ritz, nsub * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        maxres = 0;
+        bool finite = true;
+        for (int64_t j = 0; j < nsub; ++j) finite = finite && std::isfinite(hr[j]) && std::isfinite(hritz[j]);
+        for (int64_t j = 0; j < n_wanted; ++j) maxres = std::max(maxres, hr[j]);
+        if (hist_res) hist_res[it] = maxres;
+        if (!finite) { status = fail(c, CHFSI_E_NONFINITE, "non-finite residual or Ritz value"); break; }
+        if (first_res < 0) first_res = maxres;
+        if (maxres > 1e6 * std::max(first_res, 1e-300) && maxres > 1.0) {
+            status = fail(c, CHFSI_E_DIVERGED, "residual grew by more than 1e6 (lambda_max too small?)");
+            break;
+        }
+        if (!o->fixed_iters && maxres < o->tol) { converged = 1; break; }
+        if (it >= o->max_iter) break;
+        bounds[0] = hritz[0];
+        bounds[1] = hritz[nsub - 1];
+        if (!(bounds[0] < bounds[1] && bounds[1] < bounds[2])) {
+            status = fail(c, CHFSI_E_BOUNDS, "Ritz values exceed lambda_max: bounds not ordered");
+            break;
+        }
+        HIPCHK(c, hipEventRecord(ev[1], s));
+        if ((rc = filter_impl(c, o->prec, o->degree, bounds, X, ritz, R, X, nsub, ld, s))) { status = rc; break; }
+        HIPCHK(c, hipEventRecord(ev[2], s));
+        if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { status = rc; break; }
+        HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
+        if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { status = rc; break; }
+        if ((rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s))) { status = rc; break; }
+        HIPCHK(c, hipEventRecord(ev[3], s));
+        HIPCHK(c, hipEventSynchronize(ev[3]));
+        float ms1 = 0, ms2 = 0;
+        hipEventElapsedTime(&ms1, ev[1], ev[2]);
+        hipEventElapsedTime(&ms2, ev[2], ev[3]);
+        t_filter += ms1 * 1e-3;
+        t_rr += ms2 * 1e-3;
+        titer.push_back((ms1 + ms2) * 1e-3);
+    }
+    HIPCHK(c, hipEventRecord(ev[3], s));
+    HIPCHK(c, hipEventSynchronize(ev[3]));
+    float mst = 0;
+    hipEventElapsedTime(&mst, ev[0], ev[3]);
+    cleanup();
+    HIPCHK(c, hipMemcpy(eigvals, ritz, n_wanted * 8, hipMemcpyDeviceToHost));
+    if (rep) {
+        rep->iters = it;
+        rep->converged = converged;
+        rep->max_res = maxres;
+        rep->lambda_bounds[0] = bounds[0];
+        rep->lambda_bounds[1] = bounds[1];
+        rep->lambda_bounds[2] = lmax;
+        rep->t_filter = t_filter;
+        rep->t_rr = t_rr;
+        rep->t_total = mst * 1e-3;
+        std::vector<double> tt(titer.size() > 1 ? titer.begin() + 1 : titer.begin(), titer.end());
+        std::sort(tt.begin(), tt.end());
+        rep->t_iter_median = tt.empty() ? 0 : tt[tt.size() / 2];
+    }
+    if (status != CHFSI_OK) return status;
+    return converged || o->fixed_iters ? CHFSI_OK : CHFSI_NOT_CONVERGED;
+}
+
+int chfsi_info(const chfsi_ctx *c, int64_t *nnodes, int64_t *ncells, int *n, int *nq) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (nnodes) *nnodes = c->m.M;
+    if (ncells) *ncells = c->m.ncells;
+    if (n) *n = c->m.n;
+    if (nq) *nq = c->m.nq;
+    return CHFSI_OK;
+}
+
+int chfsi_mass_diag(chfsi_ctx *c, double *D, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (!D) return fail(c, CHFSI_E_ARG, "D is NULL");
+    HIPCHK(c, hipMemcpyAsync(D, c->P<double>(c->L.D64), c->m.M * 8, hipMemcpyDeviceToDevice, S(stream)));
+    return CHFSI_OK;
+}
+
+const char *chfsi_last_error(const chfsi_ctx *c) {
+    if (c) return c->err.c_str();
+    return g_err.c_str();
+}
+
+void chfsi_destroy(chfsi_ctx *c) {
+    if (!c) return;
+    if (c->blas) rocblas_destroy_handle(c->blas);
+    delete c;
+}
+
+}  // extern "C"

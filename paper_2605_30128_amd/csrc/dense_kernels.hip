@@ -1,0 +1,335 @@
+// Small dense FP64 kernels of the Rayleigh-Ritz stage (matrices of the
+// subspace size N, row-major complex128): Hermitian equilibration, Cholesky
+// factorisation, the triangular inverse that turns a Cholesky factor into
+// the orthonormalizing transform, and the dense Hermitian eigensolve
+// (parallel cyclic Jacobi: every round rotates N/2 disjoint index pairs in a
+// round-robin order, reading the previous iterate and writing the next one,
+// so one launch per round has no intra-launch dependencies).
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace chfsi {
+
+// ---------------------------------------------------------------------------
+// S <- diag(s) (S + S^H)/2 diag(s), s_i = 1 / sqrt(Re S_ii)
+// ---------------------------------------------------------------------------
+__global__ void equil_scale_kernel(int N, const cd *S, double *scale, int *flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double d = S[(int64_t)i * N + i].x;
+    if (!(d > 0.0) || !isfinite(d)) {
+        *flag = 1;
+        scale[i] = 1.0;
+    } else {
+        scale[i] = 1.0 / sqrt(d);
+    }
+}
+
+__global__ void equil_apply_kernel(int N, cd *S, const double *scale) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    int i = (int)(idx / N), j = (int)(idx % N);
+    if (j > i) return;  // lower thread handles the pair (i, j), (j, i)
+    cd a = S[(int64_t)i * N + j], b = S[(int64_t)j * N + i];
+    double sc = scale ? scale[i] * scale[j] : 1.0;
+    cd h;
+    h.x = 0.5 * (a.x + b.x) * sc;
+    h.y = 0.5 * (a.y - b.y) * sc;
+    S[(int64_t)i * N + j] = h;
+    h.y = -h.y;
+    if (i == j) h.y = 0;
+    S[(int64_t)j * N + i] = h;
+}
+
+hipError_t launch_herm_equilibrate(int N, cd *S, double *scale, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(equil_scale_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, S, scale, flag);
+    int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(equil_apply_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, S, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_hermitize(int N, cd *S, hipStream_t s) {
+    int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(equil_apply_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, S,
+                       (const double *)nullptr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// in-place Cholesky A = L L^H (lower; the strict upper triangle is zeroed).
+// One workgroup: right-looking, column by column.  flag = 1 on a
+// non-positive pivot.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void cholesky_kernel(int N, cd *A, int *flag) {
+    __shared__ double djj;
+    __shared__ int bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < N; ++j) {
+        if (tid == 0) {
+            double d = A[(int64_t)j * N + j].x;
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad = 1;
+                d = 1.0;
+            }
+            djj = sqrt(d);
+            A[(int64_t)j * N + j] = cd{djj, 0.0};
+        }
+        __syncthreads();
+        if (bad) break;
+        const double inv = 1.0 / djj;
+        for (int i = j + 1 + tid; i < N; i += nt) {
+            cd v = A[(int64_t)i * N + j];
+            v.x *= inv;
+            v.y *= inv;
+            A[(int64_t)i * N + j] = v;
+        }
+        __syncthreads();
+        const int m = N - j - 1;
+        for (int64_t idx = tid; idx < (int64_t)m * m; idx += nt) {
+            int i = j + 1 + (int)(idx / m), k = j + 1 + (int)(idx % m);
+            if (k > i) continue;
+            cd lij = A[(int64_t)i * N + j], lkj = A[(int64_t)k * N + j];
+            cd a = A[(int64_t)i * N + k];
+            // a -= lij * conj(lkj)
+            a.x -= lij.x * lkj.x + lij.y * lkj.y;
+            a.y -= lij.y * lkj.x - lij.x * lkj.y;
+            A[(int64_t)i * N + k] = a;
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (tid == 0) *flag = 1;
+        return;
+    }
+    for (int64_t idx = tid; idx < (int64_t)N * N; idx += nt) {
+        int i = (int)(idx / N), k = (int)(idx % N);
+        if (k > i) A[idx] = cd{0.0, 0.0};
+    }
+}
+
+hipError_t launch_cholesky(int N, cd *A, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, s, N, A, flag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// T = diag(scale) L^{-H}: solve L^H T = I (upper triangular T), one column
+// per thread, all threads walking the rows in lock step (broadcast reads of L).
+// ---------------------------------------------------------------------------
+__global__ void tri_inv_kernel(int N, const cd *L, const double *scale, cd *T) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = c < N;
+    for (int i = N - 1; i >= 0; --i) {
+        if (!act) continue;
+        cd s;
+        if (i > c) {
+            T[(int64_t)i * N + c] = cd{0.0, 0.0};
+            continue;
+        }
+        s.x = (i == c) ? 1.0 : 0.0;
+        s.y = 0.0;
+        for (int m = i + 1; m <= c; ++m) {
+            cd l = L[(int64_t)m * N + i];  // (L^H)[i][m] = conj(L[m][i])
+            cd t = T[(int64_t)m * N + c];
+            s.x -= l.x * t.x + l.y * t.y;
+            s.y -= l.x * t.y - l.y * t.x;
+        }
+        double d = L[(int64_t)i * N + i].x;
+        T[(int64_t)i * N + c] = cd{s.x / d, s.y / d};
+    }
+    if (!act) return;
+    if (scale)
+        for (int i = 0; i <= c; ++i) {
+            cd t = T[(int64_t)i * N + c];
+            t.x *= scale[i];
+            t.y *= scale[i];
+            T[(int64_t)i * N + c] = t;
+        }
+}
+
+hipError_t launch_tri_inv_scale(int N, const cd *L, const double *scale, cd *T, hipStream_t s) {
+    hipLaunchKernelGGL(tri_inv_kernel, dim3((N + 63) / 64), dim3(64), 0, s, N, L, scale, T);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// parallel cyclic Jacobi
+// ---------------------------------------------------------------------------
+// round-robin pairing of N2 (even) indices: index 0 fixed, the rest rotate
+__device__ __forceinline__ void rr_pair(int i, int r, int N2, int &a, int &b) {
+    auto pos = [&](int k) { return k == 0 ? 0 : 1 + (k - 1 + r) % (N2 - 1); };
+    a = pos(i);
+    b = pos(N2 - 1 - i);
+    if (a > b) { int t = a; a = b; b = t; }
+}
+
+struct Rot { double c, s; cd ph; bool id; };  // G = diag(1, conj(ph)) [[c, s], [-s, c]]
+
+__device__ __forceinline__ Rot make_rot(const cd *A, int N, int a, int b) {
+    Rot R;
+    R.c = 1; R.s = 0; R.ph = cd{1, 0}; R.id = true;
+    if (b >= N) return R;
+    cd apq = A[(int64_t)a * N + b];
+    double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+    if (mag == 0.0) return R;
+    double app = A[(int64_t)a * N + a].x, aqq = A[(int64_t)b * N + b].x;
+    double tau = (aqq - app) / (2.0 * mag);
+    double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    R.c = 1.0 / sqrt(1.0 + t * t);
+    R.s = t * R.c;
+    R.ph = cd{apq.x / mag, apq.y / mag};
+    R.id = false;
+    return R;
+}
+
+// G entries: gaa = c, gab = s, gba = -s conj(ph), gbb = c conj(ph)
+__device__ __forceinline__ void rot_entries(const Rot &R, cd &gaa, cd &gab, cd &gba, cd &gbb) {
+    gaa = cd{R.c, 0};
+    gab = cd{R.s, 0};
+    gba = cd{-R.s * R.ph.x, R.s * R.ph.y};
+    gbb = cd{R.c * R.ph.x, -R.c * R.ph.y};
+}
+
+__device__ __forceinline__ cd cmul(cd a, cd b) { return cd{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cd cconj(cd a) { return cd{a.x, -a.y}; }
+
+// one round: A2 = G^H A G, V2 = V G (G block diagonal over the round's pairs)
+__global__ void jacobi_round_kernel(int N, int N2, int r, const cd *A, cd *A2, const cd *V, cd *V2) {
+    const int H = N2 / 2;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nblk = (int64_t)H * H;
+    if (idx < nblk) {
+        int bi = (int)(idx / H), bj = (int)(idx % H);
+        int a1, b1, a2, b2;
+        rr_pair(bi, r, N2, a1, b1);
+        rr_pair(bj, r, N2, a2, b2);
+        Rot R1 = make_rot(A, N, a1, b1), R2 = make_rot(A, N, a2, b2);
+        cd g1[4], g2[4];
+        rot_entries(R1, g1[0], g1[1], g1[2], g1[3]);
+        rot_entries(R2, g2[0], g2[1], g2[2], g2[3]);
+        auto ld = [&](int x, int y) { return (x < N && y < N) ? A[(int64_t)x * N + y] : cd{0, 0}; };
+        cd m00 = ld(a1, a2), m01 = ld(a1, b2), m10 = ld(b1, a2), m11 = ld(b1, b2);
+        // T = M G2
+        cd t00 = cadd(cmul(m00, g2[0]), cmul(m01, g2[2]));
+        cd t01 = cadd(cmul(m00, g2[1]), cmul(m01, g2[3]));
+        cd t10 = cadd(cmul(m10, g2[0]), cmul(m11, g2[2]));
+        cd t11 = cadd(cmul(m10, g2[1]), cmul(m11, g2[3]));
+        // G1^H T
+        cd n00 = cadd(cmul(cconj(g1[0]), t00), cmul(cconj(g1[2]), t10));
+        cd n01 = cadd(cmul(cconj(g1[0]), t01), cmul(cconj(g1[2]), t11));
+        cd n10 = cadd(cmul(cconj(g1[1]), t00), cmul(cconj(g1[3]), t10));
+        cd n11 = cadd(cmul(cconj(g1[1]), t01), cmul(cconj(g1[3]), t11));
+        if (bi == bj && !R1.id) {  // the annihilated pivot block
+            n01 = cd{0, 0};
+            n10 = cd{0, 0};
+            n00.y = 0;
+            n11.y = 0;
+        }
+        if (a1 < N && a2 < N) A2[(int64_t)a1 * N + a2] = n00;
+        if (a1 < N && b2 < N) A2[(int64_t)a1 * N + b2] = n01;
+        if (b1 < N && a2 < N) A2[(int64_t)b1 * N + a2] = n10;
+        if (b1 < N && b2 < N) A2[(int64_t)b1 * N + b2] = n11;
+        return;
+    }
+    idx -= nblk;
+    if (idx >= (int64_t)N * H) return;
+    int x = (int)(idx / H), bj = (int)(idx % H);
+    int a2, b2;
+    rr_pair(bj, r, N2, a2, b2);
+    Rot R2 = make_rot(A, N, a2, b2);
+    cd g[4];
+    rot_entries(R2, g[0], g[1], g[2], g[3]);
+    cd va = a2 < N ? V[(int64_t)x * N + a2] : cd{0, 0};
+    cd vb = b2 < N ? V[(int64_t)x * N + b2] : cd{0, 0};
+    if (a2 < N) V2[(int64_t)x * N + a2] = cadd(cmul(va, g[0]), cmul(vb, g[2]));
+    if (b2 < N) V2[(int64_t)x * N + b2] = cadd(cmul(va, g[1]), cmul(vb, g[3]));
+}
+
+__global__ void identity_kernel(int N, cd *V) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    int i = (int)(idx / N), j = (int)(idx % N);
+    V[idx] = cd{i == j ? 1.0 : 0.0, 0.0};
+}
+
+// red[0] = sum_{i != j} |A_ij|^2, red[1] = sum_i |A_ii|^2 (one workgroup, fixed order)
+__global__ void offnorm_kernel(int N, const cd *A, double *out) {
+    __shared__ double so[256], sd[256];
+    double o = 0, d = 0;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)N * N; idx += blockDim.x) {
+        int i = (int)(idx / N), j = (int)(idx % N);
+        cd v = A[idx];
+        double m2 = v.x * v.x + v.y * v.y;
+        if (i == j) d += m2; else o += m2;
+    }
+    so[threadIdx.x] = o;
+    sd[threadIdx.x] = d;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            so[threadIdx.x] += so[threadIdx.x + w];
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = so[0]; out[1] = sd[0]; }
+}
+
+// w = Re diag(A) sorted ascending (ties by index), columns of V permuted alike
+__global__ void sort_eig_kernel(int N, const cd *A, const cd *V, double *wout, cd *Vout) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    int x = (int)(idx / N), i = (int)(idx % N);
+    double wi = A[(int64_t)i * N + i].x;
+    int rank = 0;
+    for (int j = 0; j < N; ++j) {
+        double wj = A[(int64_t)j * N + j].x;
+        rank += (wj < wi) || (wj == wi && j < i);
+    }
+    Vout[(int64_t)x * N + rank] = V[(int64_t)x * N + i];
+    if (x == 0) wout[rank] = wi;
+}
+
+hipError_t launch_jacobi_eig(int N, cd *A, cd *A2, cd *V, cd *V2, double *w, double *red,
+                             int max_sweeps, hipStream_t s, int *sweeps_out, cd **Vout) {
+    // A (input, destroyed), A2/V/V2 workspaces; on return *Vout = eigenvectors
+    // (columns, ascending) in one of V/V2, w = eigenvalues.
+    const int N2 = N + (N & 1);
+    const int H = N2 / 2;
+    int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(identity_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, V);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    cd *a = A, *a2 = A2, *v = V, *v2 = V2;
+    double host[2];
+    int sweep = 0;
+    const int64_t nthr = (int64_t)H * H + (int64_t)N * H;
+    for (; sweep < max_sweeps; ++sweep) {
+        hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(256), 0, s, N, a, red);
+        err = hipMemcpyAsync(host, red, sizeof(host), hipMemcpyDeviceToHost, s);
+        if (err != hipSuccess) return err;
+        err = hipStreamSynchronize(s);
+        if (err != hipSuccess) return err;
+        if (!(std::isfinite(host[0]) && std::isfinite(host[1]))) return hipErrorInvalidValue;
+        if (host[0] <= 1e-30 * (host[0] + host[1]) || N < 2) break;
+        for (int r = 0; r < N2 - 1; ++r) {
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, N, N2, r,
+                               a, a2, v, v2);
+            std::swap(a, a2);
+            std::swap(v, v2);
+        }
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (sweeps_out) *sweeps_out = sweep;
+    hipLaunchKernelGGL(sort_eig_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, a, v, w, v2);
+    *Vout = v2;
+    return hipGetLastError();
+}
+
+}  // namespace chfsi

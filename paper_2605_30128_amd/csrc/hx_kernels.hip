@@ -1,0 +1,701 @@
+// Matrix-free cell-level Hamiltonian-times-multivector product for gfx950.
+//
+// Stages follow the paper's product (Sec. III-C2, stages i-iv): gather of the
+// cell block, dense cell contraction, spin-orbit projector term, assembly.
+// The local cell operator of eq. cellHam is applied in factored form:
+//     Y^(e) = K X^(e) + Phi^T [ w|J| (V_q I + B_q . sigma) ] (Phi X^(e)),
+// with K the reference stiffness (1/2 grad N . grad N, identical for every
+// cell of the uniform mesh) and Phi[q][I] = N_I(x_q).  This is the same
+// 2n x 2n spin-block operator of eq. cellHam (H_scal = K + V-mass, H_Bd =
+// B_d-mass) without storing four n x n matrices per cell.
+//
+// MFMA tiling.  Every cell block is treated as a GEMM with rows = real
+// columns of the vector block (re/im x spin x vector) and columns = nodes or
+// quadrature points.  One workgroup (4 waves) owns one cell and VB vectors;
+// each wave owns one 16-row tile and a slice of the column tiles.  The
+// gathered block sits in LDS as [node][real column]; the shared tables (K,
+// Phi, Phi^T) are read as MFMA B fragments straight from L2.  The 16x16
+// accumulator layout puts the four real columns (re up, im up, re down, im
+// down) of one vector at one quadrature point into one lane, so the 2x2
+// spin term is applied in registers.  Assembly is colour-ordered: the eight
+// parity classes of cells are launched one after another, so no two
+// workgroups of a launch touch the same node and no atomics are needed
+// (results are deterministic).
+#include "internal.h"
+
+namespace chfsi {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MM;
+template <> struct MM<double> {
+    using acc = d4;
+    static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MM<float> {
+    using acc = f4;
+    static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+// Workgroup ids are dealt to the 8 XCDs round robin; map them so that the
+// workgroups of one XCD take a contiguous range of logical tiles (the vector
+// blocks of the same cells share that XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
+    int64_t q = total >> 3, r = total & 7;
+    int64_t x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+struct CellParams {
+    const void *X;
+    void *Y;
+    int64_t ld, nvec;
+    const int *cells;
+    int64_t ncl;
+    int px, py, pz;
+    int64_t ncx, ncy, Nx, Ny, Nz;
+    int p, n1, n;
+    const void *Bk, *BphiT, *Bphi, *W, *dinv;
+    double alpha;
+    const int *cell_pair_ptr, *cell_pairs, *pair_atom;
+    const void *P, *dcoef;
+    int nbeta;
+    int64_t ldd;
+    int mode, flags;
+};
+
+__device__ __forceinline__ int64_t gnode_of(int ijk, int64_t ex, int64_t ey, int64_t ez, int p,
+                                            int64_t Nx, int64_t Ny, int64_t Nz) {
+    int64_t gx = ex * p + (ijk & 255), gy = ey * p + ((ijk >> 8) & 255), gz = ez * p + (ijk >> 16);
+    gx -= gx >= Nx ? Nx : 0;
+    gy -= gy >= Ny ? Ny : 0;
+    gz -= gz >= Nz ? Nz : 0;
+    return gx + Nx * (gy + Ny * gz);
+}
+
+template <typename T> struct LdsPad { static constexpr int v = 4; };
+template <> struct LdsPad<float> { static constexpr int v = 8; };
+
+// Row (GEMM M index) of component `comp` (re up, im up, re down, im down) of
+// vector v of the block.  The 16x16 accumulators hold, in lane l and
+// register i, row 4*(l/16)+i for the f32 MFMA but row 4*i+l/16 for the f64
+// MFMA; the order below puts the four components of vector 4m + l/16 into
+// registers 0..3 of lane l in both cases.
+template <typename T> __device__ __forceinline__ constexpr int rcol(int v, int comp) {
+    return sizeof(T) == 8 ? 16 * (v >> 2) + 4 * comp + (v & 3) : 4 * v + comp;
+}
+
+// Gathers the vector block of one cell into LDS as xs[I][rcol(v, 2s + r)].
+template <typename T, int VB, int NP, int XS>
+__device__ __forceinline__ void gather_block(T *xs, const int *ijk, const void *Xv, int64_t ld,
+                                             int64_t nvec, int64_t col0, int n, int64_t ex,
+                                             int64_t ey, int64_t ez, int p, int64_t Nx,
+                                             int64_t Ny, int64_t Nz, const T *dinv) {
+    using TC = typename Cplx<T>::type;
+    const TC *X = reinterpret_cast<const TC *>(Xv);
+    for (int idx = threadIdx.x; idx < NP * 2 * VB; idx += kThreads) {
+        int v = idx % VB;
+        int s = (idx / VB) & 1;
+        int I = idx / (2 * VB);
+        int64_t col = col0 + v;
+        T re = 0, im = 0;
+        if (I < n && col < nvec) {
+            int64_t g = gnode_of(ijk[I], ex, ey, ez, p, Nx, Ny, Nz);
+            TC z = X[(2 * g + s) * ld + col];
+            T sc = dinv ? dinv[g] : T(1);
+            re = z.x * sc;
+            im = z.y * sc;
+        }
+        xs[I * XS + rcol<T>(v, 2 * s)] = re;
+        xs[I * XS + rcol<T>(v, 2 * s + 1)] = im;
+    }
+}
+
+// acc[t] += A^T(rows 16m.., k) * B(k, cols (nt0+t)*16..) over k in [0, NP):
+// A from LDS (as[k][c]), B from global ([k][NP] row-major).
+template <typename T, int NTW, int NP, int XS>
+__device__ __forceinline__ void mfma_panel(typename MM<T>::acc *acc, const T *as, const T *B, int m,
+                                           int nt0, int lane) {
+    const int kr = lane >> 4, cn = lane & 15;
+    const T *bp = B + (size_t)kr * NP + nt0 * 16 + cn;
+    const T *ap = as + kr * XS + 16 * m + cn;
+#pragma unroll 2
+    for (int kk = 0; kk < NP; kk += 4) {
+        T av = ap[kk * XS];
+        const T *brow = bp + (size_t)kk * NP;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, brow[16 * t], acc[t]);
+    }
+}
+
+template <typename T, int MT, int NP>
+__global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
+    using TC = typename Cplx<T>::type;
+    using acc_t = typename MM<T>::acc;
+    constexpr int CB = 16 * MT, VB = 4 * MT;
+    constexpr int XS = CB + LdsPad<T>::v;
+    constexpr int NT = NP / 16, WN = 4 / MT, NTW = NT / WN;
+    static_assert(NT % WN == 0, "tile split");
+    __shared__ __attribute__((aligned(16))) T xs[NP * XS];
+    __shared__ int ijk[NP];
+
+    const int64_t nvb = (a.nvec + VB - 1) / VB;
+    const int64_t t_log = xcd_remap(blockIdx.x, a.ncl * nvb);
+    const int64_t ci = t_log / nvb, vb = t_log - ci * nvb;
+    const int64_t e = a.cells[ci];
+    const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = wave % MT, nt0 = (wave / MT) * NTW;
+
+    for (int I = tid; I < NP; I += kThreads) {
+        int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
+        ijk[I] = i | (j << 8) | (k << 16);
+    }
+    __syncthreads();
+    gather_block<T, VB, NP, XS>(xs, ijk, a.X, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
+                                a.Ny, a.Nz,
+                                (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr);
+    __syncthreads();
+
+    acc_t y[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) y[t] = acc_t{0, 0, 0, 0};
+    mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bk), m, nt0, lane);
+
+    if (a.mode == MODE_HAM) {
+        acc_t tq[NTW];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) tq[t] = acc_t{0, 0, 0, 0};
+        mfma_panel<T, NTW, NP, XS>(tq, xs, reinterpret_cast<const T *>(a.BphiT), m, nt0, lane);
+        // pointwise (V + B.sigma) w|J| on (re up, im up, re down, im down)
+        const T *W = reinterpret_cast<const T *>(a.W) + (size_t)e * NP * 4;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            int q = (nt0 + t) * 16 + (lane & 15);
+            T v = W[q * 4 + 0], bx = W[q * 4 + 1], by = W[q * 4 + 2], bz = W[q * 4 + 3];
+            T ur = tq[t][0], ui = tq[t][1], dr = tq[t][2], di = tq[t][3];
+            tq[t][0] = (v + bz) * ur + bx * dr + by * di;
+            tq[t][1] = (v + bz) * ui + bx * di - by * dr;
+            tq[t][2] = bx * ur - by * ui + (v - bz) * dr;
+            tq[t][3] = bx * ui + by * ur + (v - bz) * di;
+        }
+        __syncthreads();  // every wave is done reading the gathered block
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            int q = (nt0 + t) * 16 + (lane & 15);
+            const int vl = 4 * m + (lane >> 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xs[q * XS + rcol<T>(vl, i)] = tq[t][i];
+        }
+        __syncthreads();
+        mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
+
+        if ((a.flags & FLAG_NLOC) && a.cell_pair_ptr) {
+            const int64_t col = vb * VB + 4 * m + (lane >> 4);
+            const int pb = a.cell_pair_ptr[e], pe = a.cell_pair_ptr[e + 1];
+            if (col < a.nvec) {
+                for (int pp = pb; pp < pe; ++pp) {
+                    const int pair = a.cell_pairs[pp];
+                    const int atom = a.pair_atom[pair];
+                    const TC *P = reinterpret_cast<const TC *>(a.P) + (size_t)pair * NP * 2 * a.nbeta;
+                    const TC *dc = reinterpret_cast<const TC *>(a.dcoef) + (size_t)atom * a.nbeta * a.ldd + col;
+                    for (int j = 0; j < a.nbeta; ++j) {
+                        TC d = dc[(size_t)j * a.ldd];
+#pragma unroll
+                        for (int t = 0; t < NTW; ++t) {
+                            int J = (nt0 + t) * 16 + (lane & 15);
+                            TC p0 = P[(J * 2 + 0) * a.nbeta + j];
+                            TC p1 = P[(J * 2 + 1) * a.nbeta + j];
+                            y[t][0] += p0.x * d.x - p0.y * d.y;
+                            y[t][1] += p0.x * d.y + p0.y * d.x;
+                            y[t][2] += p1.x * d.x - p1.y * d.y;
+                            y[t][3] += p1.x * d.y + p1.y * d.x;
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // colour-ordered assembly
+    TC *Y = reinterpret_cast<TC *>(a.Y);
+    const int64_t col = vb * VB + 4 * m + (lane >> 4);
+    if (col < a.nvec) {
+        const T al = (T)a.alpha;
+        const bool accum = (a.flags & FLAG_ACCUM) != 0;
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            int J = (nt0 + t) * 16 + (lane & 15);
+            if (J < a.n) {
+                int c = ijk[J];
+                int i = c & 255, j = (c >> 8) & 255, k = c >> 16;
+                int64_t g = gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+                // first colour to reach this node: parity 0 in every face direction
+                bool fx = (i == 0 || i == a.p), fy = (j == 0 || j == a.p), fz = (k == 0 || k == a.p);
+                bool first = !accum && !(fx && a.px) && !(fy && a.py) && !(fz && a.pz);
+                TC *d0 = Y + (2 * g) * a.ld + col;
+                TC *d1 = d0 + a.ld;
+                TC v0, v1;
+                v0.x = al * y[t][0]; v0.y = al * y[t][1];
+                v1.x = al * y[t][2]; v1.y = al * y[t][3];
+                if (!first) {
+                    TC o0 = *d0, o1 = *d1;
+                    v0.x += o0.x; v0.y += o0.y;
+                    v1.x += o1.x; v1.y += o1.y;
+                }
+                *d0 = v0;
+                *d1 = v1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// nonlocal projection: part[pair][j][col] = sum_{I,s} conj(P[pair][I][s][j]) x[I][s][col]
+// ---------------------------------------------------------------------------
+struct ProjParams {
+    const void *X;
+    int64_t ld, nvec;
+    const int *cells;  // cells with at least one pair
+    int64_t ncl;
+    int64_t ncx, ncy, Nx, Ny, Nz;
+    int p, n1, n;
+    const void *dinv;
+    const int *cell_pair_ptr, *cell_pairs;
+    const void *P;
+    void *part;
+    int nbeta;
+    int flags;
+};
+
+template <typename T, int MT, int NP>
+__global__ __launch_bounds__(kThreads) void proj_kernel(ProjParams a) {
+    using TC = typename Cplx<T>::type;
+    constexpr int VB = 4 * MT, CB = 16 * MT;
+    constexpr int XS = CB + LdsPad<T>::v;
+    __shared__ T xs[NP * XS];
+    __shared__ int ijk[NP];
+    __shared__ TC red[kThreads];
+
+    const int64_t nvb = (a.nvec + VB - 1) / VB;
+    const int64_t t_log = xcd_remap(blockIdx.x, a.ncl * nvb);
+    const int64_t ci = t_log / nvb, vb = t_log - ci * nvb;
+    const int64_t e = a.cells[ci];
+    const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
+    const int tid = threadIdx.x;
+    for (int I = tid; I < NP; I += kThreads) {
+        int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
+        ijk[I] = i | (j << 8) | (k << 16);
+    }
+    __syncthreads();
+    gather_block<T, VB, NP, XS>(xs, ijk, a.X, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
+                                a.Ny, a.Nz,
+                                (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr);
+    __syncthreads();
+    const int nout = VB * a.nbeta;
+    const int nsplit = kThreads / nout;
+    const int o = tid % nout, split = tid / nout;
+    const int j = o / VB, v = o % VB;
+    const int64_t col = vb * VB + v;
+    const int pb = a.cell_pair_ptr[e], pe = a.cell_pair_ptr[e + 1];
+    for (int pp = pb; pp < pe; ++pp) {
+        const int pair = a.cell_pairs[pp];
+        const TC *P = reinterpret_cast<const TC *>(a.P) + (size_t)pair * NP * 2 * a.nbeta;
+        TC acc;
+        acc.x = 0; acc.y = 0;
+        if (split < nsplit) {
+            for (int I = split; I < a.n; I += nsplit) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    TC pc = P[(I * 2 + s) * a.nbeta + j];
+                    T xr = xs[I * XS + rcol<T>(v, 2 * s)], xi = xs[I * XS + rcol<T>(v, 2 * s + 1)];
+                    acc.x += pc.x * xr + pc.y * xi;
+                    acc.y += pc.x * xi - pc.y * xr;
+                }
+            }
+        }
+        red[tid] = acc;
+        __syncthreads();
+        if (split == 0) {
+            TC s = red[o];
+            for (int k = 1; k < nsplit; ++k) {
+                s.x += red[k * nout + o].x;
+                s.y += red[k * nout + o].y;
+            }
+            if (col < a.nvec)
+                reinterpret_cast<TC *>(a.part)[((size_t)pair * a.nbeta + j) * a.nvec + col] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// dcoef[atom][i][col] = sum_j Delta[atom][i][j] * sum_{pairs of atom} part[pair][j][col]
+template <typename TC>
+__global__ void nl_reduce_kernel(const TC *part, const int *atom_pair_ptr, const cd *delta,
+                                 TC *dcoef, int64_t natoms, int nbeta, int64_t nvec) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= natoms * nvec) return;
+    int64_t atom = idx / nvec, col = idx % nvec;
+    double sr[kMaxBeta], si[kMaxBeta];
+    for (int j = 0; j < nbeta; ++j) { sr[j] = 0; si[j] = 0; }
+    for (int pr = atom_pair_ptr[atom]; pr < atom_pair_ptr[atom + 1]; ++pr)
+        for (int j = 0; j < nbeta; ++j) {
+            TC v = part[((size_t)pr * nbeta + j) * nvec + col];
+            sr[j] += v.x;
+            si[j] += v.y;
+        }
+    const cd *D = delta + (size_t)atom * nbeta * nbeta;
+    for (int i = 0; i < nbeta; ++i) {
+        double ar = 0, ai = 0;
+        for (int j = 0; j < nbeta; ++j) {
+            cd d = D[i * nbeta + j];
+            ar += d.x * sr[j] - d.y * si[j];
+            ai += d.x * si[j] + d.y * sr[j];
+        }
+        TC o;
+        o.x = ar; o.y = ai;
+        dcoef[((size_t)atom * nbeta + i) * nvec + col] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint with respect to the quadrature fields
+// ---------------------------------------------------------------------------
+struct AdjParams {
+    const void *X, *G;
+    int64_t ld, nvec;
+    int64_t ncells, ncx, ncy, Nx, Ny, Nz;
+    int p, n1, n, nq;
+    const void *BphiT;
+    const double *wq;
+    double *dV, *dB;
+};
+
+template <typename T, int MT, int NP>
+__global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams a) {
+    using acc_t = typename MM<T>::acc;
+    constexpr int VB = 4 * MT, CB = 16 * MT;
+    constexpr int XS = CB + LdsPad<T>::v;
+    constexpr int NT = NP / 16, WN = 4 / MT, NTW = NT / WN;
+    __shared__ __attribute__((aligned(16))) T xs[NP * XS];
+    __shared__ int ijk[NP];
+    static_assert(NP * XS * sizeof(T) >= 4 * NP * sizeof(double), "reduction buffer");
+
+    const int64_t e = blockIdx.x;
+    const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = wave % MT, nt0 = (wave / MT) * NTW;
+    for (int I = tid; I < NP; I += kThreads) {
+        int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
+        ijk[I] = i | (j << 8) | (k << 16);
+    }
+    double sv[NTW], sx[NTW], sy[NTW], sz[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) { sv[t] = 0; sx[t] = 0; sy[t] = 0; sz[t] = 0; }
+    const T *BphiT = reinterpret_cast<const T *>(a.BphiT);
+    const int64_t nvb = (a.nvec + VB - 1) / VB;
+    for (int64_t vb = 0; vb < nvb; ++vb) {
+        __syncthreads();
+        gather_block<T, VB, NP, XS>(xs, ijk, a.X, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
+                                    a.Ny, a.Nz, nullptr);
+        __syncthreads();
+        acc_t tx[NTW], tg[NTW];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) { tx[t] = acc_t{0, 0, 0, 0}; tg[t] = acc_t{0, 0, 0, 0}; }
+        mfma_panel<T, NTW, NP, XS>(tx, xs, BphiT, m, nt0, lane);
+        __syncthreads();
+        gather_block<T, VB, NP, XS>(xs, ijk, a.G, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
+                                    a.Ny, a.Nz, nullptr);
+        __syncthreads();
+        mfma_panel<T, NTW, NP, XS>(tg, xs, BphiT, m, nt0, lane);
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            double xur = tx[t][0], xui = tx[t][1], xdr = tx[t][2], xdi = tx[t][3];
+            double gur = tg[t][0], gui = tg[t][1], gdr = tg[t][2], gdi = tg[t][3];
+            sv[t] += gur * xur + gui * xui + gdr * xdr + gdi * xdi;
+            // Re(conj(gu) xd + conj(gd) xu)
+            sx[t] += gur * xdr + gui * xdi + gdr * xur + gdi * xui;
+            // Im(conj(gu) xd) - Im(conj(gd) xu)
+            sy[t] += (gur * xdi - gui * xdr) - (gdr * xui - gdi * xur);
+            sz[t] += gur * xur + gui * xui - gdr * xdr - gdi * xdi;
+        }
+    }
+    // reduce over the 4 vector lanes of each quadrature point (lane>>4), then over waves
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        for (int off = 16; off < 64; off <<= 1) {
+            sv[t] += __shfl_xor(sv[t], off);
+            sx[t] += __shfl_xor(sx[t], off);
+            sy[t] += __shfl_xor(sy[t], off);
+            sz[t] += __shfl_xor(sz[t], off);
+        }
+    }
+    __syncthreads();  // the block tile is free: reuse it for the reduction
+    double *red = reinterpret_cast<double *>(xs);
+    for (int i = tid; i < 4 * NP; i += kThreads) red[i] = 0;
+    __syncthreads();
+    // deterministic order over the MT waves sharing a column slice
+    for (int mm = 0; mm < MT; ++mm) {
+        if (m == mm && lane < 16) {
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                int q = (nt0 + t) * 16 + lane;
+                red[0 * NP + q] += sv[t];
+                red[1 * NP + q] += sx[t];
+                red[2 * NP + q] += sy[t];
+                red[3 * NP + q] += sz[t];
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < a.nq; q += kThreads) {
+        double w = a.wq[q];
+        a.dV[e * a.nq + q] = w * red[0 * NP + q];
+        a.dB[(e * a.nq + q) * 3 + 0] = w * red[1 * NP + q];
+        a.dB[(e * a.nq + q) * 3 + 1] = w * red[2 * NP + q];
+        a.dB[(e * a.nq + q) * 3 + 2] = w * red[3 * NP + q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+__global__ void setup_fields_kernel(const double *V, const double *B, const double *wq, double *W64,
+                                    float *W32, int64_t ncells, int nq, int NP) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ncells * NP) return;
+    int64_t e = idx / NP;
+    int q = (int)(idx % NP);
+    double v = 0, bx = 0, by = 0, bz = 0;
+    if (q < nq) {
+        double w = wq[q];
+        v = w * V[e * nq + q];
+        bx = w * B[(e * nq + q) * 3 + 0];
+        by = w * B[(e * nq + q) * 3 + 1];
+        bz = w * B[(e * nq + q) * 3 + 2];
+    }
+    double *o = W64 + idx * 4;
+    o[0] = v; o[1] = bx; o[2] = by; o[3] = bz;
+    float *f = W32 + idx * 4;
+    f[0] = (float)v; f[1] = (float)bx; f[2] = (float)by; f[3] = (float)bz;
+}
+
+// P[pair][I][s][j] = sum_q wq[q] Phi[q][I] phi[pair][q][s][j]
+__global__ void setup_proj_kernel(const cd *phi, const double *Phi, const double *wq, cd *P64,
+                                  cf *P32, int64_t npairs, int n, int nq, int NP, int nbeta) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t per = (int64_t)NP * 2 * nbeta;
+    if (idx >= npairs * per) return;
+    int64_t pair = idx / per;
+    int r = (int)(idx % per);
+    int I = r / (2 * nbeta), sj = r % (2 * nbeta);
+    double ar = 0, ai = 0;
+    if (I < n) {
+        const cd *ph = phi + (size_t)pair * nq * 2 * nbeta + sj;
+        for (int q = 0; q < nq; ++q) {
+            double w = wq[q] * Phi[(size_t)q * NP + I];
+            cd z = ph[(size_t)q * 2 * nbeta];
+            ar += w * z.x;
+            ai += w * z.y;
+        }
+    }
+    P64[idx].x = ar; P64[idx].y = ai;
+    P32[idx].x = (float)ar; P32[idx].y = (float)ai;
+}
+
+__global__ void cast_table_kernel(const double *src, float *dst, __bf16 *dstb, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = (float)src[i];
+    if (dstb) dstb[i] = (__bf16)(float)src[i];
+}
+
+__global__ void dinv_kernel(const double *D, double *d64, float *d32, int64_t M) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    double v = 1.0 / D[i];
+    d64[i] = v;
+    d32[i] = (float)v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int MT, int NP>
+static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha, const void *X,
+                           void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+    const Mesh &m = c->m;
+    const Layout &L = c->L;
+    constexpr bool dbl = sizeof(T) == 8;
+    CellParams a{};
+    a.X = X; a.Y = Y; a.ld = ld; a.nvec = nvec;
+    a.ncx = m.ncell[0]; a.ncy = m.ncell[1];
+    a.Nx = m.Nd[0]; a.Ny = m.Nd[1]; a.Nz = m.Nd[2];
+    a.p = m.p; a.n1 = m.n1; a.n = m.n;
+    if (mode == MODE_MASS) a.Bk = c->P<char>(L.M64);
+    else a.Bk = dbl ? c->P<char>(L.K64) : c->P<char>(L.K32);
+    a.BphiT = dbl ? c->P<char>(L.PhiT64) : c->P<char>(L.PhiT32);
+    a.Bphi = dbl ? c->P<char>(L.Phi64) : c->P<char>(L.Phi32);
+    a.W = dbl ? c->P<char>(L.W64) : c->P<char>(L.W32);
+    a.dinv = dbl ? c->P<char>(L.Dinv64) : c->P<char>(L.Dinv32);
+    a.alpha = alpha;
+    a.mode = mode;
+    a.flags = flags;
+    if ((flags & FLAG_NLOC) && m.npairs > 0) {
+        a.cell_pair_ptr = c->P<int>(L.cell_pair_ptr);
+        a.cell_pairs = c->P<int>(L.cell_pairs);
+        a.pair_atom = c->P<int>(L.pair_atom);
+        a.P = dbl ? c->P<char>(L.P64) : c->P<char>(L.P32);
+        a.dcoef = c->S<char>(L.dcoef);
+        a.nbeta = m.nbeta;
+        a.ldd = nvec;
+    } else {
+        a.flags &= ~FLAG_NLOC;
+    }
+    constexpr int VB = 4 * MT;
+    const int64_t nvb = (nvec + VB - 1) / VB;
+    for (int col = 0; col < 8; ++col) {
+        int64_t ncl = c->colour_ptr[col + 1] - c->colour_ptr[col];
+        if (ncl == 0) continue;
+        a.cells = c->P<int>(L.colour_cells) + c->colour_ptr[col];
+        a.ncl = ncl;
+        a.px = col & 1; a.py = (col >> 1) & 1; a.pz = (col >> 2) & 1;
+        hipLaunchKernelGGL((cell_kernel<T, MT, NP>), dim3((unsigned)(ncl * nvb)), dim3(kThreads), 0, s, a);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+template <typename T, int MT, int NP>
+static hipError_t run_proj(const chfsi_ctx *c, int flags, const void *X, int64_t nvec, int64_t ld,
+                           hipStream_t s) {
+    const Mesh &m = c->m;
+    const Layout &L = c->L;
+    constexpr bool dbl = sizeof(T) == 8;
+    ProjParams a{};
+    a.X = X; a.ld = ld; a.nvec = nvec;
+    a.cells = c->P<int>(L.nl_cells);
+    a.ncl = m.n_nl_cells;
+    a.ncx = m.ncell[0]; a.ncy = m.ncell[1];
+    a.Nx = m.Nd[0]; a.Ny = m.Nd[1]; a.Nz = m.Nd[2];
+    a.p = m.p; a.n1 = m.n1; a.n = m.n;
+    a.dinv = dbl ? c->P<char>(L.Dinv64) : c->P<char>(L.Dinv32);
+    a.cell_pair_ptr = c->P<int>(L.cell_pair_ptr);
+    a.cell_pairs = c->P<int>(L.cell_pairs);
+    a.P = dbl ? c->P<char>(L.P64) : c->P<char>(L.P32);
+    a.part = c->S<char>(L.partial);
+    a.nbeta = m.nbeta;
+    a.flags = flags;
+    constexpr int VB = 4 * MT;
+    const int64_t nvb = (nvec + VB - 1) / VB;
+    hipLaunchKernelGGL((proj_kernel<T, MT, NP>), dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int64_t nthr = m.natoms * nvec;
+    if (dbl)
+        hipLaunchKernelGGL(nl_reduce_kernel<cd>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s,
+                           c->S<cd>(L.partial), c->P<int>(L.atom_pair_ptr), c->P<cd>(L.delta64),
+                           c->S<cd>(L.dcoef), m.natoms, m.nbeta, nvec);
+    else
+        hipLaunchKernelGGL(nl_reduce_kernel<cf>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s,
+                           c->S<cf>(L.partial), c->P<int>(L.atom_pair_ptr), c->P<cd>(L.delta64),
+                           c->S<cf>(L.dcoef), m.natoms, m.nbeta, nvec);
+    return hipGetLastError();
+}
+
+template <typename T, int MT, int NP>
+static hipError_t run_adjoint(const chfsi_ctx *c, const void *X, const void *G, int64_t nvec,
+                              int64_t ld, double *dV, double *dB, hipStream_t s) {
+    const Mesh &m = c->m;
+    const Layout &L = c->L;
+    constexpr bool dbl = sizeof(T) == 8;
+    AdjParams a{};
+    a.X = X; a.G = G; a.ld = ld; a.nvec = nvec;
+    a.ncells = m.ncells; a.ncx = m.ncell[0]; a.ncy = m.ncell[1];
+    a.Nx = m.Nd[0]; a.Ny = m.Nd[1]; a.Nz = m.Nd[2];
+    a.p = m.p; a.n1 = m.n1; a.n = m.n; a.nq = m.nq;
+    a.BphiT = dbl ? c->P<char>(L.PhiT64) : c->P<char>(L.PhiT32);
+    a.wq = c->P<double>(L.Wq);
+    a.dV = dV; a.dB = dB;
+    hipLaunchKernelGGL((adjoint_kernel<T, MT, NP>), dim3((unsigned)m.ncells), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// dispatch on the padded table size (one instantiation per FE degree class)
+#define CHFSI_DISPATCH_NP(NPV, CALL)          \
+    switch (NPV) {                            \
+    case 32: { constexpr int NP = 32; CALL; } \
+    case 64: { constexpr int NP = 64; CALL; } \
+    case 128: { constexpr int NP = 128; CALL; } \
+    case 224: { constexpr int NP = 224; CALL; } \
+    case 352: { constexpr int NP = 352; CALL; } \
+    case 512: { constexpr int NP = 512; CALL; } \
+    default: return hipErrorInvalidValue;     \
+    }
+
+hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
+                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+    if (prec == CHFSI_FP64) {
+        CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
+    }
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 4, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
+}
+
+hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags, const void *X,
+                                  int64_t nvec, int64_t ld, hipStream_t s) {
+    if (c->m.npairs == 0 || c->m.n_nl_cells == 0) return hipSuccess;
+    if (prec == CHFSI_FP64) {
+        CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<double, 2, NP>(c, flags, X, nvec, ld, s)));
+    }
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<float, 4, NP>(c, flags, X, nvec, ld, s)));
+}
+
+hipError_t launch_adjoint_fields(const chfsi_ctx *c, chfsi_prec prec, const void *X, const void *G,
+                                 int64_t nvec, int64_t ld, double *dV, double *dB, hipStream_t s) {
+    if (prec == CHFSI_FP64) {
+        CHFSI_DISPATCH_NP(c->m.npad, return (run_adjoint<double, 2, NP>(c, X, G, nvec, ld, dV, dB, s)));
+    }
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_adjoint<float, 4, NP>(c, X, G, nvec, ld, dV, dB, s)));
+}
+
+hipError_t launch_setup_fields(const chfsi_ctx *c, const double *V, const double *B, hipStream_t s) {
+    const int64_t nthr = c->m.ncells * c->m.npad;
+    hipLaunchKernelGGL(setup_fields_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, V, B,
+                       c->P<double>(c->L.Wq), c->P<double>(c->L.W64), c->P<float>(c->L.W32),
+                       c->m.ncells, c->m.nq, c->m.npad);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_projectors(const chfsi_ctx *c, const cd *phi_dev, hipStream_t s) {
+    const Mesh &m = c->m;
+    if (m.npairs == 0) return hipSuccess;
+    const int64_t nthr = m.npairs * m.npad * 2 * m.nbeta;
+    hipLaunchKernelGGL(setup_proj_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, phi_dev,
+                       c->P<double>(c->L.Phi64), c->P<double>(c->L.Wq), c->P<cd>(c->L.P64),
+                       c->P<cf>(c->L.P32), m.npairs, m.n, m.nq, m.npad, m.nbeta);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup_casts(const chfsi_ctx *c, hipStream_t s) {
+    const Layout &L = c->L;
+    const int64_t nn = (int64_t)c->m.npad * c->m.npad;
+    const unsigned g = (unsigned)((nn + 255) / 256);
+    hipLaunchKernelGGL(cast_table_kernel, dim3(g), dim3(256), 0, s, c->P<double>(L.K64), c->P<float>(L.K32),
+                       c->P<__bf16>(L.Kb), nn);
+    hipLaunchKernelGGL(cast_table_kernel, dim3(g), dim3(256), 0, s, c->P<double>(L.Phi64),
+                       c->P<float>(L.Phi32), c->P<__bf16>(L.Phib), nn);
+    hipLaunchKernelGGL(cast_table_kernel, dim3(g), dim3(256), 0, s, c->P<double>(L.PhiT64),
+                       c->P<float>(L.PhiT32), c->P<__bf16>(L.PhiTb), nn);
+    const int64_t M = c->m.M;
+    hipLaunchKernelGGL(dinv_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, c->P<double>(L.D64),
+                       c->P<double>(L.Dinv64), c->P<float>(L.Dinv32), M);
+    return hipGetLastError();
+}
+
+}  // namespace chfsi

@@ -1,0 +1,138 @@
+// Internal declarations of the MI355X R-ChFSI library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/chfsi.h"
+
+namespace chfsi {
+
+constexpr int kThreads = 256;       // threads per workgroup of the cell kernels
+constexpr int kMaxN = 512;          // nodes per cell (p <= 7)
+constexpr int kMaxBeta = 16;
+constexpr int kMaxDegree = 256;     // Chebyshev degree limit (Lambda_k table)
+
+// complex helpers ------------------------------------------------------------
+struct cd { double x, y; };
+struct cf { float x, y; };
+
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = cd; };
+template <> struct Cplx<float> { using type = cf; };
+
+// Byte offsets of the tables in the persistent buffer and of the temporaries
+// in the scratch buffer; computed identically by plan and setup.
+struct Layout {
+    // persistent
+    size_t K64, Phi64, PhiT64, M64;          // n-pad square tables (double)
+    size_t K32, Phi32, PhiT32;               // float copies
+    size_t Kb, Phib, PhiTb;                  // bfloat16 copies
+    size_t W64, W32;                         // [ncells][nqpad][4]
+    size_t Wq;                               // [nqpad] quadrature weight * |J|
+    size_t D64, Dinv64, Dinv32;              // [M]
+    size_t colour_cells;                     // int32 [ncells]
+    size_t nl_cells;                         // int32 [n_nl_cells]
+    size_t cell_pair_ptr, cell_pairs;        // int32 [ncells+1], [npairs]
+    size_t pair_atom, atom_pair_ptr;         // int32 [npairs], [natoms+1]
+    size_t P64, P32;                         // complex [npairs][npad][2][nbeta]
+    size_t delta64;                          // complex128 [natoms][nbeta][nbeta]
+    size_t persistent_bytes;
+    // scratch
+    size_t partial, dcoef;                   // complex128 [npairs|natoms][nbeta][max_nvec]
+    size_t Z;                                // 3 blocks complex128 [2M][max_nvec]
+    size_t lamk;                             // double [kMaxDegree+1][max_nvec]
+    size_t small;                            // dense N x N matrices for RR
+    size_t red;                              // reduction partials
+    size_t flag;                             // int flags
+    size_t scratch_bytes;
+    size_t small_bytes, red_bytes;
+};
+
+struct Mesh {
+    int64_t ncell[3];
+    double h[3];
+    int p, n1, n, nq1, nq, npad, nqpad;
+    int64_t ncells, M, Nd[3];
+    int64_t natoms, npairs, n_nl_cells;
+    int nbeta;
+};
+
+}  // namespace chfsi
+
+struct chfsi_ctx {
+    chfsi::Mesh m;
+    chfsi::Layout L;
+    int64_t max_nvec;
+    char *pers;
+    char *scr;
+    int64_t colour_ptr[9];
+    rocblas_handle blas;
+    std::string err;
+    // typed views
+    template <typename T> T *P(size_t off) const { return reinterpret_cast<T *>(pers + off); }
+    template <typename T> T *S(size_t off) const { return reinterpret_cast<T *>(scr + off); }
+};
+
+namespace chfsi {
+
+// ---------------------------------------------------------------- kernels
+// cell operator modes
+enum : int {
+    MODE_HAM = 0,       // H: kinetic + (V + B.sigma) + nonlocal epilogue
+    MODE_MASS = 1,      // M: mass table only
+};
+enum : int {
+    FLAG_ACCUM = 1,     // Y += alpha * (.) at every node (else first touch writes)
+    FLAG_DINV = 2,      // gather D^{-1} X
+    FLAG_NLOC = 4,      // add the spin-orbit epilogue (needs dcoef)
+};
+
+// apply the cell operator for all 8 colours: Y (+)= alpha * Op(X)
+hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
+                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s);
+// nonlocal projection + per-atom reduction with Delta: dcoef = Delta * P^H X
+hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags, const void *X,
+                                  int64_t nvec, int64_t ld, hipStream_t s);
+// adjoint fields
+hipError_t launch_adjoint_fields(const chfsi_ctx *c, chfsi_prec prec, const void *X, const void *G,
+                                 int64_t nvec, int64_t ld, double *dV, double *dB, hipStream_t s);
+// setup kernels
+hipError_t launch_setup_fields(const chfsi_ctx *c, const double *V, const double *B, hipStream_t s);
+hipError_t launch_setup_projectors(const chfsi_ctx *c, const cd *phi_dev, hipStream_t s);
+hipError_t launch_setup_casts(const chfsi_ctx *c, hipStream_t s);
+
+// elementwise (filter / residual / reductions)
+hipError_t launch_filter_init_ld(int64_t rows, int64_t nvec, int64_t ldz, int64_t ldr, bool zf32,
+                                 void *Znew, const void *Zk, const void *Zkm, const cd *R, double beta,
+                                 double gamma, const double *delta, double rscale, hipStream_t s);
+hipError_t launch_lamk_table(const double *ritz, int64_t nvec, int degree, double c, double e,
+                             double s1, double *lamk, int64_t ldl, hipStream_t s);
+hipError_t launch_recover_ld(int64_t rows, int64_t nvec, int64_t ldz, int64_t ld, bool zf32, const void *Z,
+                             const double *dinv, const cd *X, const double *lamq, cd *Y, hipStream_t s);
+hipError_t launch_residual(int64_t rows, int64_t nvec, int64_t ld, const cd *HX, const cd *MX,
+                           const double *ritz, cd *R, double *red, double *norms, hipStream_t s);
+hipError_t launch_colnorm2(int64_t rows, int64_t nvec, int64_t ld, const cd *A, const double *w,
+                           double *red, double *out, hipStream_t s);
+hipError_t launch_cast_block(int64_t rows, int64_t nvec, int64_t ld, const void *src, bool src32,
+                             void *dst, bool dst32, hipStream_t s);
+hipError_t launch_scale_rows(int64_t rows, int64_t nvec, int64_t ld, const double *w, cd *A,
+                             hipStream_t s);
+hipError_t launch_check_finite(const double *a, int64_t n, int *flag, hipStream_t s);
+hipError_t launch_dot_real(int64_t n, const cd *a, const cd *b, double *red, double *out,
+                           hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const cd *x, double b, cd *y, hipStream_t s);
+
+// dense (small N x N, row-major complex128)
+hipError_t launch_herm_equilibrate(int N, cd *S, double *scale, int *flag, hipStream_t s);
+hipError_t launch_hermitize(int N, cd *S, hipStream_t s);
+hipError_t launch_cholesky(int N, cd *A, int *flag, hipStream_t s);
+hipError_t launch_tri_inv_scale(int N, const cd *L, const double *scale, cd *T, hipStream_t s);
+hipError_t launch_jacobi_eig(int N, cd *A, cd *A2, cd *V, cd *V2, double *w, double *red,
+                             int max_sweeps, hipStream_t s, int *sweeps_out, cd **Vout);
+
+}  // namespace chfsi

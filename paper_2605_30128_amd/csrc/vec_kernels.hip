@@ -1,0 +1,295 @@
+// Streaming kernels of the R-ChFSI filter and of the residual (HBM-bound):
+// the three-term update of eq. rChFSIrecurrence without its H term, the
+// Chebyshev-filtered Ritz values Lambda_k, the recovery Y = D^{-1} Z_q +
+// X Lambda_q, the residual R = HX - MX Lambda with column norms, and small
+// helpers.  Column reductions are two-stage with a fixed summation order, so
+// every result is deterministic.
+#include "internal.h"
+
+namespace chfsi {
+
+constexpr int kRowBlocks = 256;  // row blocks of the column reductions
+
+template <typename TZ> struct ZT;
+template <> struct ZT<cd> { using real = double; };
+template <> struct ZT<cf> { using real = float; };
+
+// Znew = beta*Zk + gamma*Zkm + (rscale * lam[c]) * R   (lam == nullptr: 1)
+template <typename TZ>
+__global__ void filter_init_kernel(int64_t rows, int64_t nvec, int64_t ldz, int64_t ldr, TZ *Znew,
+                                   const TZ *Zk, const TZ *Zkm, const cd *R, double beta, double gamma,
+                                   const double *lam, double rscale) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nvec) return;
+    const double d = rscale * (lam ? lam[c] : 1.0);
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        int64_t o = r * ldz + c;
+        cd rr = R[r * ldr + c];
+        double vx = d * rr.x, vy = d * rr.y;
+        if (Zk) { vx += beta * (double)Zk[o].x; vy += beta * (double)Zk[o].y; }
+        if (Zkm) { vx += gamma * (double)Zkm[o].x; vy += gamma * (double)Zkm[o].y; }
+        TZ z;
+        z.x = (typename ZT<TZ>::real)vx;
+        z.y = (typename ZT<TZ>::real)vy;
+        Znew[o] = z;
+    }
+}
+
+static dim3 col_grid(int64_t nvec, int64_t rows, unsigned &threads) {
+    threads = nvec >= 256 ? 256 : (nvec >= 128 ? 128 : 64);
+    unsigned gx = (unsigned)((nvec + threads - 1) / threads);
+    int64_t want = (4096 + gx - 1) / gx;  // enough workgroups to fill the chip
+    unsigned gy = (unsigned)(want < rows ? want : rows);
+    if (gy < 1) gy = 1;
+    if (gy > 65535) gy = 65535;
+    return dim3(gx, gy);
+}
+
+hipError_t launch_filter_init_ld(int64_t rows, int64_t nvec, int64_t ldz, int64_t ldr, bool zf32,
+                                 void *Znew, const void *Zk, const void *Zkm, const cd *R, double beta,
+                                 double gamma, const double *delta, double rscale, hipStream_t s) {
+    unsigned th;
+    dim3 g = col_grid(nvec, rows, th);
+    if (zf32)
+        hipLaunchKernelGGL(filter_init_kernel<cf>, g, dim3(th), 0, s, rows, nvec, ldz, ldr, (cf *)Znew,
+                           (const cf *)Zk, (const cf *)Zkm, R, beta, gamma, delta, rscale);
+    else
+        hipLaunchKernelGGL(filter_init_kernel<cd>, g, dim3(th), 0, s, rows, nvec, ldz, ldr, (cd *)Znew,
+                           (const cd *)Zk, (const cd *)Zkm, R, beta, gamma, delta, rscale);
+    return hipGetLastError();
+}
+
+// lamk[k][c] = C_k-recurrence of the Ritz value ritz[c]: Lambda_0 = 1,
+// Lambda_1 = s1 (lambda - c)/e, Lambda_{k+1} = (2 s_{k+1}/e)(lambda - c)
+// Lambda_k - s_k s_{k+1} Lambda_{k-1}, s_{k+1} = 1/(2/s1 - s_k).
+__global__ void lamk_kernel(const double *ritz, int64_t nvec, int degree, double c, double e,
+                            double s1, double *lamk, int64_t ldl) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nvec) return;
+    double lam = ritz[j];
+    double lm = 1.0, l0 = s1 * (lam - c) / e, sk = s1;
+    lamk[j] = 1.0;
+    if (degree >= 1) lamk[ldl + j] = l0;
+    for (int k = 1; k < degree; ++k) {
+        double sn = 1.0 / (2.0 / s1 - sk);
+        double ln = 2.0 * sn / e * (lam - c) * l0 - sk * sn * lm;
+        lamk[(int64_t)(k + 1) * ldl + j] = ln;
+        lm = l0;
+        l0 = ln;
+        sk = sn;
+    }
+}
+
+hipError_t launch_lamk_table(const double *ritz, int64_t nvec, int degree, double c, double e,
+                             double s1, double *lamk, int64_t ldl, hipStream_t s) {
+    hipLaunchKernelGGL(lamk_kernel, dim3((unsigned)((nvec + 255) / 256)), dim3(256), 0, s, ritz, nvec,
+                       degree, c, e, s1, lamk, ldl);
+    return hipGetLastError();
+}
+
+// Y = D^{-1} Z + X diag(lamq)
+template <typename TZ>
+__global__ void recover_kernel(int64_t rows, int64_t nvec, int64_t ldz, int64_t ld, const TZ *Z,
+                               const double *dinv, const cd *X, const double *lamq, cd *Y) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nvec) return;
+    const double l = lamq[c];
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        int64_t o = r * ld + c;
+        double di = dinv[r >> 1];
+        TZ z = Z[r * ldz + c];
+        cd x = X[o];
+        cd y;
+        y.x = di * (double)z.x + l * x.x;
+        y.y = di * (double)z.y + l * x.y;
+        Y[o] = y;
+    }
+}
+
+hipError_t launch_recover_ld(int64_t rows, int64_t nvec, int64_t ldz, int64_t ld, bool zf32, const void *Z,
+                             const double *dinv, const cd *X, const double *lamq, cd *Y, hipStream_t s) {
+    unsigned th;
+    dim3 g = col_grid(nvec, rows, th);
+    if (zf32)
+        hipLaunchKernelGGL(recover_kernel<cf>, g, dim3(th), 0, s, rows, nvec, ldz, ld, (const cf *)Z, dinv, X,
+                           lamq, Y);
+    else
+        hipLaunchKernelGGL(recover_kernel<cd>, g, dim3(th), 0, s, rows, nvec, ldz, ld, (const cd *)Z, dinv, X,
+                           lamq, Y);
+    return hipGetLastError();
+}
+
+// R = HX - MX diag(ritz); red[rb][c] = sum over the row block of |R|^2
+__global__ void residual_kernel(int64_t rows, int64_t nvec, int64_t ld, const cd *HX, const cd *MX,
+                                const double *ritz, cd *R, double *red) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nvec) return;
+    const double l = ritz[c];
+    const int64_t per = (rows + gridDim.y - 1) / gridDim.y;
+    const int64_t r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+    double s = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+        int64_t o = r * ld + c;
+        cd h = HX[o], m = MX[o];
+        cd v;
+        v.x = h.x - l * m.x;
+        v.y = h.y - l * m.y;
+        if (R) R[o] = v;
+        s += v.x * v.x + v.y * v.y;
+    }
+    red[(int64_t)blockIdx.y * nvec + c] = s;
+}
+
+__global__ void col_finish_kernel(const double *red, int nb, int64_t nvec, double *out, int do_sqrt) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nvec) return;
+    double s = 0;
+    for (int b = 0; b < nb; ++b) s += red[(int64_t)b * nvec + c];
+    out[c] = do_sqrt ? sqrt(s) : s;
+}
+
+hipError_t launch_residual(int64_t rows, int64_t nvec, int64_t ld, const cd *HX, const cd *MX,
+                           const double *ritz, cd *R, double *red, double *norms, hipStream_t s) {
+    unsigned th = nvec >= 256 ? 256 : 64;
+    dim3 g((unsigned)((nvec + th - 1) / th), kRowBlocks);
+    hipLaunchKernelGGL(residual_kernel, g, dim3(th), 0, s, rows, nvec, ld, HX, MX, ritz, R, red);
+    if (norms)
+        hipLaunchKernelGGL(col_finish_kernel, dim3((unsigned)((nvec + 255) / 256)), dim3(256), 0, s, red,
+                           kRowBlocks, nvec, norms, 1);
+    return hipGetLastError();
+}
+
+// sum over rows of w[r/2] |A[r][c]|^2 (w == nullptr: 1)
+__global__ void colnorm2_kernel(int64_t rows, int64_t nvec, int64_t ld, const cd *A, const double *w,
+                                double *red) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nvec) return;
+    const int64_t per = (rows + gridDim.y - 1) / gridDim.y;
+    const int64_t r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+    double s = 0;
+    for (int64_t r = r0; r < r1; ++r) {
+        cd v = A[r * ld + c];
+        double ww = w ? w[r >> 1] : 1.0;
+        s += ww * (v.x * v.x + v.y * v.y);
+    }
+    red[(int64_t)blockIdx.y * nvec + c] = s;
+}
+
+hipError_t launch_colnorm2(int64_t rows, int64_t nvec, int64_t ld, const cd *A, const double *w,
+                           double *red, double *out, hipStream_t s) {
+    unsigned th = nvec >= 256 ? 256 : 64;
+    dim3 g((unsigned)((nvec + th - 1) / th), kRowBlocks);
+    hipLaunchKernelGGL(colnorm2_kernel, g, dim3(th), 0, s, rows, nvec, ld, A, w, red);
+    hipLaunchKernelGGL(col_finish_kernel, dim3((unsigned)((nvec + 255) / 256)), dim3(256), 0, s, red,
+                       kRowBlocks, nvec, out, 0);
+    return hipGetLastError();
+}
+
+template <typename TS, typename TD>
+__global__ void cast_kernel(int64_t rows, int64_t nvec, int64_t ld, const TS *src, TD *dst) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nvec) return;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        TS v = src[r * ld + c];
+        TD o;
+        o.x = v.x;
+        o.y = v.y;
+        dst[r * ld + c] = o;
+    }
+}
+
+hipError_t launch_cast_block(int64_t rows, int64_t nvec, int64_t ld, const void *src, bool src32,
+                             void *dst, bool dst32, hipStream_t s) {
+    unsigned th;
+    dim3 g = col_grid(nvec, rows, th);
+    if (src32 && !dst32)
+        hipLaunchKernelGGL((cast_kernel<cf, cd>), g, dim3(th), 0, s, rows, nvec, ld, (const cf *)src, (cd *)dst);
+    else if (!src32 && dst32)
+        hipLaunchKernelGGL((cast_kernel<cd, cf>), g, dim3(th), 0, s, rows, nvec, ld, (const cd *)src, (cf *)dst);
+    else if (src32)
+        hipLaunchKernelGGL((cast_kernel<cf, cf>), g, dim3(th), 0, s, rows, nvec, ld, (const cf *)src, (cf *)dst);
+    else
+        hipLaunchKernelGGL((cast_kernel<cd, cd>), g, dim3(th), 0, s, rows, nvec, ld, (const cd *)src, (cd *)dst);
+    return hipGetLastError();
+}
+
+// A[r][c] *= w[r/2]
+__global__ void scale_rows_kernel(int64_t rows, int64_t nvec, int64_t ld, const double *w, cd *A) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nvec) return;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        double ww = w[r >> 1];
+        cd v = A[r * ld + c];
+        v.x *= ww;
+        v.y *= ww;
+        A[r * ld + c] = v;
+    }
+}
+
+hipError_t launch_scale_rows(int64_t rows, int64_t nvec, int64_t ld, const double *w, cd *A,
+                             hipStream_t s) {
+    unsigned th;
+    dim3 g = col_grid(nvec, rows, th);
+    hipLaunchKernelGGL(scale_rows_kernel, g, dim3(th), 0, s, rows, nvec, ld, w, A);
+    return hipGetLastError();
+}
+
+__global__ void finite_kernel(const double *a, int64_t n, int *flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!isfinite(a[i])) bad = 1;
+    if (bad) *flag = 1;  // benign race: every writer stores 1
+}
+
+hipError_t launch_check_finite(const double *a, int64_t n, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(finite_kernel, dim3(1024), dim3(256), 0, s, a, n, flag);
+    return hipGetLastError();
+}
+
+// out = Re sum conj(a_i) b_i (two stages, fixed order)
+__global__ void dot_partial_kernel(int64_t n, const cd *a, const cd *b, double *red) {
+    __shared__ double sm[256];
+    double s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s += a[i].x * b[i].x + a[i].y * b[i].y;
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) red[blockIdx.x] = sm[0];
+}
+
+__global__ void dot_finish_kernel(const double *red, int nb, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0;
+        for (int i = 0; i < nb; ++i) s += red[i];
+        *out = s;
+    }
+}
+
+hipError_t launch_dot_real(int64_t n, const cd *a, const cd *b, double *red, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(512), dim3(256), 0, s, n, a, b, red);
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(1), dim3(64), 0, s, red, 512, out);
+    return hipGetLastError();
+}
+
+// y = a x + b y
+__global__ void axpby_kernel(int64_t n, double a, const cd *x, double b, cd *y) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        cd v = y[i];
+        cd u = x ? x[i] : cd{0, 0};
+        v.x = a * u.x + b * v.x;
+        v.y = a * u.y + b * v.y;
+        y[i] = v;
+    }
+}
+
+hipError_t launch_axpby(int64_t n, double a, const cd *x, double b, cd *y, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(1024), dim3(256), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+}  // namespace chfsi

@@ -127,9 +127,13 @@ def min_image(d: np.ndarray, box: np.ndarray) -> np.ndarray:
 
 def gaussian_wells(pts: np.ndarray, centres: np.ndarray, depths: np.ndarray,
                    box: np.ndarray, width: float = WELL_WIDTH) -> np.ndarray:
-    """V(r) = -sum_w d_w exp(-|r-c_w|^2/(2 width^2)) over the 27 nearest images."""
+    """V(r) = -sum_w d_w exp(-|r-c_w|^2/(2 width^2)) over the periodic images
+    within 10 widths (of the 27 nearest, an image shifted along a direction
+    whose half box exceeds 10 widths never comes that close and is skipped)."""
     V = np.zeros(pts.shape[:-1])
-    shifts = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)], float)
+    reach = 10.0 * width
+    shifts = [np.array([i, j, k], float) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]
+    shifts = [s for s in shifts if all(s[d] == 0 or 0.5 * box[d] <= reach for d in range(3))]
     for c, d in zip(centres, depths):
         base = min_image(pts - c, box)
         for s in shifts:

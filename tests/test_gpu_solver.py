@@ -1,0 +1,150 @@
+"""GPU parity of the R-ChFSI stages (filter, Cholesky-QR2, Rayleigh-Ritz,
+Lanczos bound) and of the whole eigensolver against the CPU oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2605_30128_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "tiny_rchfsi.json")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2605_30128_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def tiny_state(oracle_lib):
+    """Ritz pairs of a random 40-column block of the tiny problem (oracle)."""
+    p = synth.make_config("tiny")
+    o = oracle_lib.Oracle(p)
+    X0 = synth.random_block(p.ndof, 40, 401)
+    Y, HY, MY = o.orthonormalize(X0, o.apply_H(X0), o.apply_M(X0))
+    X, HX, MX, ritz = o.rayleigh_ritz(Y, HY, MY)
+    R, _ = oracle_lib.residual(HX, MX, ritz)
+    lmax = o.lanczos(20, synth.random_block(p.ndof, 1, 402)[:, 0])
+    return dict(p=p, o=o, X=X, HX=HX, MX=MX, ritz=ritz, R=R, lmax=lmax, X0=X0)
+
+
+def _dev(X, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(X)).to("cuda", dtype)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_filter_parity(B, tiny_state, prec, tol):
+    s = tiny_state
+    o = s["o"]
+    bounds = [s["ritz"][0], s["ritz"][-1], s["lmax"]]
+    q = 20
+    ref = o.filter(q, bounds, s["X"], s["ritz"], s["R"])
+    op = B.Chfsi(s["p"], max_nvec=40)
+    Y = op.filter(_dev(s["X"]), torch.from_numpy(s["ritz"]), _dev(s["R"]), q, bounds, prec=prec).cpu().numpy()
+    assert _rel(Y, ref) < tol, _rel(Y, ref)
+
+
+def test_filter_degree_one_and_inplace(B, tiny_state):
+    s = tiny_state
+    o = s["o"]
+    bounds = [s["ritz"][0], s["ritz"][-1], s["lmax"]]
+    op = B.Chfsi(s["p"], max_nvec=40)
+    for q in (1, 2, 5):
+        ref = o.filter(q, bounds, s["X"], s["ritz"], s["R"])
+        Xd = _dev(s["X"])
+        op.filter(Xd, torch.from_numpy(s["ritz"]), _dev(s["R"]), q, bounds, Y=Xd)  # Y aliases X
+        assert _rel(Xd.cpu().numpy(), ref) < 1e-12
+
+
+def test_bad_bounds_rejected(B, tiny_state):
+    s = tiny_state
+    op = B.Chfsi(s["p"], max_nvec=40)
+    with pytest.raises(B.ChfsiError) as ei:
+        op.filter(_dev(s["X"]), torch.from_numpy(s["ritz"]), _dev(s["R"]), 5, [1.0, 0.5, 2.0])
+    assert ei.value.code == B.E_BOUNDS
+
+
+def test_orthonormalize_and_rr_parity(B, tiny_state, oracle_lib):
+    s = tiny_state
+    o = s["o"]
+    X0 = s["X0"]
+    HX0, MX0 = o.apply_H(X0), o.apply_M(X0)
+    Yr, HYr, MYr = o.orthonormalize(X0, HX0, MX0)
+    op = B.Chfsi(s["p"], max_nvec=40)
+    Y, HY, MY = _dev(X0), _dev(HX0), _dev(MX0)
+    op.orthonormalize(Y, HY, MY)
+    # same algorithm, same arithmetic up to rounding order
+    assert _rel(Y.cpu().numpy(), Yr) < 1e-10
+    G = Y.cpu().numpy().conj().T @ o.apply_M(Y.cpu().numpy())
+    assert np.abs(G - np.eye(40)).max() < 1e-12
+    ritz, R, res = op.rayleigh_ritz(Y, HY, MY)
+    _, _, _, ritz_r = o.rayleigh_ritz(Yr, HYr, MYr)
+    assert np.abs(ritz.cpu().numpy() - ritz_r).max() < 1e-11 * np.abs(ritz_r).max()
+    Xg = Y.cpu().numpy()
+    Rr, nr = oracle_lib.residual(o.apply_H(Xg), o.apply_M(Xg), ritz.cpu().numpy())
+    assert np.allclose(res.cpu().numpy(), nr, rtol=1e-9, atol=1e-12)
+
+
+def test_rank_deficient_block_fails(B, tiny_state):
+    s = tiny_state
+    o = s["o"]
+    X0 = s["X0"].copy()
+    X0[:, 5] = X0[:, 4]
+    op = B.Chfsi(s["p"], max_nvec=40)
+    with pytest.raises(B.ChfsiError) as ei:
+        op.orthonormalize(_dev(X0), _dev(o.apply_H(X0)), _dev(o.apply_M(X0)))
+    assert ei.value.code == B.E_NOT_SPD
+
+
+def test_lanczos_parity(B, tiny_state):
+    s = tiny_state
+    op = B.Chfsi(s["p"], max_nvec=40)
+    v0 = synth.random_block(s["p"].ndof, 1, 402)[:, 0]
+    lm = op.estimate_bounds(torch.from_numpy(v0), 20)
+    assert abs(lm - s["lmax"]) < 1e-6 * s["lmax"]
+
+
+def test_solve_tiny_fp64_matches_golden(B):
+    g = json.load(open(GOLD))
+    p = synth.make_config("tiny")
+    op = B.Chfsi(p, max_nvec=g["nsub"])
+    X = _dev(synth.random_block(p.ndof, g["nsub"], g["x0_seed"]))
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, g["lanczos_seed"])[:, 0])
+    out = op.solve(X, g["n_wanted"], g["degree"], prec="fp64", tol=1e-10, max_iter=200, v0=v0)
+    assert out["converged"], out
+    ref = np.asarray(g["eigenvalues"][:g["n_wanted"]])
+    assert np.abs(out["eigvals"] - ref).max() < 1e-10, np.abs(out["eigvals"] - ref).max()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_solve_tiny_mixed(B, prec):
+    g = json.load(open(GOLD))
+    p = synth.make_config("tiny")
+    op = B.Chfsi(p, max_nvec=g["nsub"])
+    X = _dev(synth.random_block(p.ndof, g["nsub"], g["x0_seed"]))
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, g["lanczos_seed"])[:, 0])
+    out = op.solve(X, g["n_wanted"], g["degree"], prec=prec, tol=1e-8, max_iter=200, v0=v0)
+    print(prec, "iterations", out["iters"], "max residual", out["max_res"])
+    assert out["converged"], out
+    ref = np.asarray(g["eigenvalues"][:g["n_wanted"]])
+    assert np.abs(out["eigvals"] - ref).max() < 1e-9
+
+
+def test_solve_max_iter_not_converged(B):
+    p = synth.make_config("tiny")
+    op = B.Chfsi(p, max_nvec=40)
+    X = _dev(synth.random_block(p.ndof, 40, 2001))
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, 2000)[:, 0])
+    out = op.solve(X, 32, 20, prec="fp64", tol=1e-14, max_iter=1, v0=v0)
+    assert out["status"] == B.NOT_CONVERGED and out["iters"] == 1
+    assert np.all(np.isfinite(out["eigvals"]))
