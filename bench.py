@@ -1,0 +1,204 @@
+"""Benchmark of the R-ChFSI hot path on one MI355X.
+
+A step is one R-ChFSI iteration (Algorithm RChFSI) on the medium workload:
+Chebyshev filter of degree q in the mixed precision (the filter's H D^-1 Z
+products), recovery, H Y and M Y in double, Cholesky-QR2, Rayleigh-Ritz and
+the double-precision residual.  `value` is the number of H X dof-vectors
+the timed steps processed per second (q products of the nsub-column block per
+iteration), i.e. whole-job H X throughput including the Rayleigh-Ritz stage.
+Isolated H X throughputs per precision, the double-precision iteration
+time, the roofline of the dominant kernel and the CPU oracle baseline are
+reported beside it.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16|fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
+CSIZE = {"fp64": 16, "fp32": 8, "bf16": 8}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def hx_flops(p, nvec):
+    """Algorithmic flops of one H X: local 24n^2 + 16n per cell and vector
+    (K X, Phi X and Phi^T T on four real columns, 2x2 spin term), nonlocal
+    32 n nbeta per (atom, cell) pair and vector (projection and apply)."""
+    n = (p.degree + 1) ** 3
+    local = p.ncells * nvec * (24 * n * n + 16 * n)
+    nonloc = p.npairs * nvec * 32 * n * p.nbeta
+    return local, nonloc
+
+
+def cpu_baseline(p, nvec=4):
+    import numpy as np
+
+    import oracle
+    from paper_2605_30128_amd import synth
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = oracle.Oracle(p)
+    X = synth.random_block(p.ndof, nvec, 9001)
+    t0 = time.perf_counter()
+    o.apply_H(X)
+    dt = time.perf_counter() - t0
+    return {"value": p.ndof * nvec / dt / 1e9, "unit": "GDoF*vec/s", "cores": threads, "kind": "oracle",
+            "sample": f"one H X of {nvec} vectors on the full medium mesh ({p.ndof} dofs), "
+                      f"projector tables included, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="medium")
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--hx-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-iter", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
+              "the filter would shard over column blocks of X, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2605_30128_amd import binding, synth
+
+    binding.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = synth.CONFIGS[args.config]
+    t0 = time.perf_counter()
+    p = synth.make_config(args.config)
+    log(f"[bench] generated {args.config}: {p.ndof} dofs, {p.npairs} pairs in {time.perf_counter() - t0:.1f}s")
+    nsub, nhx, q = cfg["nsub"], cfg["nvec_hx"], cfg["cheb_degree"]
+    op = binding.Chfsi(p, max_nvec=max(nsub, nhx))
+    log("[bench] setup done")
+
+    # ---- isolated H X per precision (nhx vectors)
+    hx = {}
+    prof = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
+        X = torch.from_numpy(synth.random_block(p.ndof, nhx, 7001)).to("cuda", dt)
+        Y = torch.empty_like(X)
+        for _ in range(2):
+            op.apply_H(X, prec=prec, Y=Y)
+        torch.cuda.synchronize()
+        reps = [op.profile_apply_H(X, prec=prec, Y=Y) for _ in range(args.hx_reps)]
+        cell = float(np.median([r[0] for r in reps]))
+        coef = float(np.median([r[1] for r in reps]))
+        tot = float(np.median([r[2] for r in reps]))
+        launches = reps[0][3]
+        hx[prec] = p.ndof * nhx / (tot * 1e-3) / 1e9
+        prof[prec] = dict(ms_cell=cell, ms_coeff=coef, ms_total=tot, launches=launches)
+        log(f"[bench] H X {prec}: {tot:.2f} ms ({cell:.2f} cell, {coef:.2f} coeff) -> {hx[prec]:.2f} GDoF*vec/s")
+        del X, Y
+    torch.cuda.empty_cache()
+
+    # ---- the timed steps: R-ChFSI iterations
+    n_wanted = cfg["n_wanted"]
+    X = torch.from_numpy(synth.random_block(p.ndof, nsub, 7002)).to("cuda", torch.complex128)
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, 7003)[:, 0])
+    out = op.solve(X, n_wanted, q, prec=args.prec, max_iter=max(args.warmup, 1), fixed_iters=True, v0=v0)
+    lmax = out["bounds"][2]
+    work = out["work"]
+    log(f"[bench] warmup done: residual {out['max_res']:.3e}, lambda_max {lmax:.3f}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = op.solve(X, n_wanted, q, prec=args.prec, max_iter=args.steps, fixed_iters=True, resume=True, work=work,
+                   lambda_max=lmax)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall / args.steps * 1e3
+    value = args.steps * q * p.ndof * nsub / wall / 1e9
+    log(f"[bench] {args.steps} {args.prec} iterations: {ms_step:.1f} ms/iter (filter {out['t_filter']:.3f}s, "
+        f"rr {out['t_rr']:.3f}s), residual {out['max_res']:.3e}")
+    it64 = None
+    if not args.no_fp64_iter and args.prec != "fp64":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o64 = op.solve(X, n_wanted, q, prec="fp64", max_iter=1, fixed_iters=True, resume=True, work=work,
+                       lambda_max=lmax)
+        torch.cuda.synchronize()
+        it64 = time.perf_counter() - t1
+        log(f"[bench] 1 fp64 iteration: {it64 * 1e3:.1f} ms (filter {o64['t_filter']:.3f}s)")
+
+    # ---- roofline of the dominant kernel: the cell operator in the step's precision
+    pr = args.prec
+    loc, nl = hx_flops(p, nhx)
+    launches = prof[pr]["launches"]
+    flops_launch = (loc + nl / 2) / launches  # the projection half runs in the coefficient kernels
+    bytes_launch = 2 * p.ndof * nhx * CSIZE[pr] / launches  # read X once, write Y once
+    t_launch = prof[pr]["ms_cell"] * 1e-3 / launches
+    t_flop = flops_launch / PEAK[pr]
+    t_byte = bytes_launch / PEAK["hbm"]
+    if t_flop >= t_byte:
+        roof = {"bound": "mfma", "achieved": flops_launch / t_launch / 1e12, "peak": PEAK[pr] / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_launch / t_launch / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = f"cell_kernel ({pr}), avg of {launches} colour launches per H X, {nhx} vectors"
+    roof["flops_per_launch"] = flops_launch
+    roof["bytes_per_launch"] = bytes_launch
+    roof["ms_per_launch"] = t_launch * 1e3
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(p)
+            log(f"[bench] cpu baseline: {cpu}")
+        except Exception as e:  # the baseline is a report, never the product
+            log(f"[bench] cpu baseline failed: {e}")
+
+    res = {
+        "metric": "GDoF*vec/s of H*X + sec/R-ChFSI iter, mixed vs FP64 at 1e-9 Ha eigen error",
+        "value": value,
+        "unit": "GDoF*vec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": pr,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: periodic cube {p.box[0]:g} bohr, {p.ncell[0]}x{p.ncell[1]}x{p.ncell[2]} "
+                        f"cells, p={p.degree}, {p.ndof} complex spinor dofs, {p.natoms} atoms x {p.nbeta} SOC "
+                        f"projectors, {nsub}-column subspace ({n_wanted} wanted), Chebyshev degree {q}",
+            "filter_precision": pr,
+            "rr_precision": "fp64",
+            "hx_vectors": nhx,
+            "nsub": nsub,
+        },
+        "sec_per_iter": {pr: ms_step / 1e3, "fp64": it64},
+        "hx_gdofvec_per_s": hx,
+        "hx_profile_ms": prof,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -180,6 +180,15 @@ int chfsi_orthonormalize(chfsi_ctx *ctx, void *Y, void *HY, void *MY,
 int chfsi_rayleigh_ritz(chfsi_ctx *ctx, void *Y, void *HY, void *MY, int64_t nvec, int64_t ld,
                         double *ritz, void *R, double *resnorm, void *stream);
 
+/* Rayleigh-Ritz of a block that need not be M-orthonormal (Algorithm
+ * RChFSI, RR step: Y^H H Y Q = Y^H M Y Q Lambda): S = Y^H MY, Hs = Y^H HY,
+ * s = diag(S)^{-1/2}, L L^H = diag(s) S diag(s), T = diag(s) L^{-H},
+ * (T^H Hs T) W = W Lambda, Q = T W, then Y, HY, MY <- (.) Q (so that
+ * Y^H M Y = I) and, as in chfsi_rayleigh_ritz, the residual.  Returns
+ * CHFSI_E_NOT_SPD if S is numerically singular. */
+int chfsi_rayleigh_ritz_general(chfsi_ctx *ctx, void *Y, void *HY, void *MY, int64_t nvec, int64_t ld,
+                                double *ritz, void *R, double *resnorm, void *stream);
+
 /* R = HX - MX diag(ritz) and resnorm[j] = ||R_j||_2 (complex128 blocks,
  * double device vectors). */
 int chfsi_residual(chfsi_ctx *ctx, const void *HX, const void *MX, const double *ritz,
@@ -193,6 +202,17 @@ typedef struct {
     int lanczos_steps;  /* steps of the lambda_max estimate (0: use lambda_max) */
     double lambda_max;  /* used when lanczos_steps == 0 */
     int fixed_iters;    /* if != 0, run exactly max_iter iterations (timing) */
+    int rr_mode;        /* 0: Cholesky-QR2 then Rayleigh-Ritz on the
+                           orthonormal block (chfsi_orthonormalize +
+                           chfsi_rayleigh_ritz); 1: Rayleigh-Ritz of the
+                           generalized subspace problem through one Cholesky
+                           factor of Y^H M Y (chfsi_rayleigh_ritz_general),
+                           falling back to mode 0 on a Cholesky breakdown */
+    int resume;         /* if != 0, X and the workspace hold the state left by
+                           a previous chfsi_solve on the same X and workspace
+                           (Ritz vectors, HX, MX, R, Ritz values): the initial
+                           orthonormalization, Rayleigh-Ritz and the Lanczos
+                           bound are skipped and lambda_max is taken from opts */
 } chfsi_solve_opts;
 
 typedef struct {
@@ -220,6 +240,15 @@ int chfsi_solve(chfsi_ctx *ctx, int64_t n_wanted, const chfsi_solve_opts *opts,
                 void *X, int64_t nsub, int64_t ld, const void *v0,
                 double *eigvals, double *hist_res, chfsi_report *report,
                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Instrumentation: performs one chfsi_apply_H(ctx, prec, X, Y, ...) and
+ * reports, from device events recorded on `stream` around the launches,
+ * ms[0] = milliseconds in the cell-operator launches (gather, cell
+ * contraction, projector epilogue, assembly), ms[1] = in the spin-orbit
+ * coefficient launches, ms[2] = whole product; *launches = number of
+ * cell-operator launches (one per non-empty cell colour).  Synchronizes. */
+int chfsi_profile_apply_H(chfsi_ctx *ctx, chfsi_prec prec, const void *X, void *Y, int64_t nvec,
+                          int64_t ld, double ms[3], int *launches, void *stream);
 
 /* Mesh sizes of a context: nnodes (M), ncells, n (nodes per cell), nq. */
 int chfsi_info(const chfsi_ctx *ctx, int64_t *nnodes, int64_t *ncells, int *n, int *nq);

@@ -42,7 +42,8 @@ class _Proj(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("prec", C.c_int), ("degree", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
-                ("lanczos_steps", C.c_int), ("lambda_max", C.c_double), ("fixed_iters", C.c_int)]
+                ("lanczos_steps", C.c_int), ("lambda_max", C.c_double), ("fixed_iters", C.c_int),
+                ("rr_mode", C.c_int), ("resume", C.c_int)]
 
 
 class Report(C.Structure):
@@ -54,8 +55,8 @@ class Report(C.Structure):
 SYMBOLS = [
     "chfsi_plan", "chfsi_setup", "chfsi_set_fields", "chfsi_apply_H", "chfsi_apply_M",
     "chfsi_apply_H_adjoint", "chfsi_estimate_bounds", "chfsi_filter", "chfsi_orthonormalize",
-    "chfsi_rayleigh_ritz", "chfsi_residual", "chfsi_solve_workspace", "chfsi_solve", "chfsi_info",
-    "chfsi_mass_diag", "chfsi_last_error", "chfsi_destroy",
+    "chfsi_rayleigh_ritz", "chfsi_rayleigh_ritz_general", "chfsi_residual", "chfsi_solve_workspace", "chfsi_solve", "chfsi_info",
+    "chfsi_mass_diag", "chfsi_profile_apply_H", "chfsi_last_error", "chfsi_destroy",
 ]
 
 _lib = None
@@ -80,11 +81,13 @@ def load(path: str = LIB_PATH):
     L.chfsi_filter.argtypes = [vp, i, i, vp, vp, vp, vp, vp, i64, i64, vp]
     L.chfsi_orthonormalize.argtypes = [vp, vp, vp, vp, i64, i64, vp]
     L.chfsi_rayleigh_ritz.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
+    L.chfsi_rayleigh_ritz_general.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
     L.chfsi_residual.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp]
     L.chfsi_solve_workspace.argtypes = [vp, i64, i64, vp]
     L.chfsi_solve.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp, vp, vp, vp, C.c_size_t, vp]
     L.chfsi_info.argtypes = [vp, vp, vp, vp, vp]
     L.chfsi_mass_diag.argtypes = [vp, vp, vp]
+    L.chfsi_profile_apply_H.argtypes = [vp, i, vp, vp, i64, i64, vp, vp, vp]
     L.chfsi_last_error.argtypes = [vp]
     L.chfsi_last_error.restype = C.c_char_p
     L.chfsi_destroy.argtypes = [vp]
@@ -236,13 +239,15 @@ class Chfsi:
         self._check(self.L.chfsi_orthonormalize(self.ctx, _ptr(Y), _ptr(HY), _ptr(MY), ld, ld, _stream()))
         return Y, HY, MY
 
-    def rayleigh_ritz(self, Y, HY, MY, want_residual=True):
+    def rayleigh_ritz(self, Y, HY, MY, want_residual=True, general=False):
+        """general=False: Y must be M-orthonormal; True: generalized subspace problem."""
         ld = self._block(Y, torch.complex128, "Y")
         ritz = torch.empty(ld, dtype=torch.float64, device=Y.device)
         R = torch.empty_like(Y) if want_residual else None
         res = torch.empty(ld, dtype=torch.float64, device=Y.device) if want_residual else None
-        self._check(self.L.chfsi_rayleigh_ritz(self.ctx, _ptr(Y), _ptr(HY), _ptr(MY), ld, ld, _ptr(ritz),
-                                               _ptr(R), _ptr(res), _stream()))
+        fn = self.L.chfsi_rayleigh_ritz_general if general else self.L.chfsi_rayleigh_ritz
+        self._check(fn(self.ctx, _ptr(Y), _ptr(HY), _ptr(MY), ld, ld, _ptr(ritz), _ptr(R), _ptr(res),
+                       _stream()))
         return ritz, R, res
 
     def residual(self, HX, MX, ritz):
@@ -258,16 +263,33 @@ class Chfsi:
         self._check(self.L.chfsi_mass_diag(self.ctx, _ptr(D), _stream()))
         return D
 
+    def profile_apply_H(self, X, prec="fp64", Y=None):
+        """One H X with device-event timings: (ms_cell, ms_coeff, ms_total, launches)."""
+        p = PREC[prec]
+        ld = self._block(X, cplx_dtype(p), "X")
+        Y = torch.empty_like(X) if Y is None else Y
+        ms = (C.c_double * 3)()
+        nl = C.c_int()
+        self._check(self.L.chfsi_profile_apply_H(self.ctx, p, _ptr(X), _ptr(Y), ld, ld, ms, C.byref(nl),
+                                                 _stream()))
+        return ms[0], ms[1], ms[2], nl.value
+
     def solve(self, X, n_wanted, degree, prec="fp64", tol=1e-8, max_iter=100, v0=None,
-              lanczos_steps=20, lambda_max=0.0, fixed_iters=False):
-        """Algorithm RChFSI from the start block X (overwritten with Ritz vectors)."""
+              lanczos_steps=20, lambda_max=0.0, fixed_iters=False, resume=False, work=None, rr_mode=1):
+        """Algorithm RChFSI from the start block X (overwritten with Ritz vectors).
+        resume=True continues from the state a previous call left in X and
+        `work` (returned as out['work']); lambda_max must then be given."""
         ld = self._block(X, torch.complex128, "X")
         nsub = ld
         ws = C.c_size_t()
         self._check(self.L.chfsi_solve_workspace(self.ctx, nsub, ld, C.byref(ws)))
-        work = torch.empty(ws.value, dtype=torch.uint8, device=X.device)
+        if work is None:
+            if resume:
+                raise ValueError("resume needs the workspace of the previous call")
+            work = torch.empty(ws.value, dtype=torch.uint8, device=X.device)
         opts = SolveOpts(PREC[prec], int(degree), float(tol), int(max_iter),
-                         int(lanczos_steps if v0 is not None else 0), float(lambda_max), int(fixed_iters))
+                         int(lanczos_steps if v0 is not None else 0), float(lambda_max), int(fixed_iters),
+                         int(rr_mode), int(resume))
         eig = np.zeros(n_wanted)
         hist = np.zeros(max_iter + 2)
         rep = Report()
@@ -280,4 +302,4 @@ class Chfsi:
         return dict(status=rc, eigvals=eig, iters=rep.iters, converged=bool(rep.converged),
                     max_res=rep.max_res, hist_res=hist[:rep.iters + 1], bounds=list(rep.lambda_bounds),
                     t_filter=rep.t_filter, t_rr=rep.t_rr, t_total=rep.t_total,
-                    t_iter_median=rep.t_iter_median)
+                    t_iter_median=rep.t_iter_median, work=work)

@@ -205,6 +205,10 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
     L.atom_pair_ptr = take((size_t)(m.natoms + 1) * 4);
     L.P64 = take((size_t)m.npairs * m.npad * 2 * m.nbeta * 16);
     L.P32 = take((size_t)m.npairs * m.npad * 2 * m.nbeta * 8);
+    L.kpad = (4 * m.nbeta + 31) / 32 * 32;
+    L.WP64 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 8);
+    L.WP32 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 4);
+    L.WPb = take((size_t)m.npairs * m.npad * L.kpad * 2);
     L.delta64 = take((size_t)m.natoms * m.nbeta * m.nbeta * 16);
     L.persistent_bytes = o;
 
@@ -213,7 +217,7 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
     L.dcoef = take((size_t)m.natoms * m.nbeta * max_nvec * 16);
     L.lamk = take((size_t)(kMaxDegree + 1) * max_nvec * 8);
     L.small_bytes = (size_t)max_nvec * max_nvec * 16;
-    L.small = take(7 * L.small_bytes + 2 * (size_t)max_nvec * 8);
+    L.small = take(9 * L.small_bytes + 2 * (size_t)max_nvec * 8);
     L.red_bytes = (size_t)256 * std::max<int64_t>(max_nvec, 2) * 8 + 4096 * 8;
     L.red = take(L.red_bytes);
     L.flag = take(256);
@@ -332,14 +336,54 @@ int read_flag(chfsi_ctx *c, hipStream_t s, int *out) {
 
 // S = A^H B (N x N row-major) for [rows][ld] blocks: column-major view of a
 // row-major block is its transpose, so S^T = Bcm * Acm^H in BLAS terms.
+// The reduction dimension (2M rows) is split into nb chunks computed as one
+// strided-batched product (enough workgroups for the whole chip), the
+// partial matrices summed in a fixed order.
 int gram(chfsi_ctx *c, const cd *A, const cd *B, int64_t N, int64_t ld, cd *Sm, hipStream_t s) {
     BLASCHK(c, rocblas_set_stream(c->blas, s));
     const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
-    BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, (rocblas_int)N,
-                             (rocblas_int)N, (rocblas_int)(2 * c->m.M), &one,
-                             reinterpret_cast<const rocblas_double_complex *>(B), (rocblas_int)ld,
-                             reinterpret_cast<const rocblas_double_complex *>(A), (rocblas_int)ld, &zero,
-                             reinterpret_cast<rocblas_double_complex *>(Sm), (rocblas_int)N));
+    const int64_t rows = 2 * c->m.M;
+    const size_t zcap = (c->L.scratch_bytes - c->L.Z) / sizeof(cd);
+    int64_t nb = 32;
+    while (nb > 1 && ((size_t)(nb + 1) * N * N > zcap || rows / nb < 4096)) nb /= 2;
+    auto rb = [](const cd *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
+    if (nb == 1) {
+        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose,
+                                 (rocblas_int)N, (rocblas_int)N, (rocblas_int)rows, &one, rb(B), (rocblas_int)ld,
+                                 rb(A), (rocblas_int)ld, &zero, reinterpret_cast<rocblas_double_complex *>(Sm),
+                                 (rocblas_int)N));
+        return CHFSI_OK;
+    }
+    cd *part = c->S<cd>(c->L.Z);
+    const int64_t chunk = rows / nb, tail = rows - nb * chunk;
+    BLASCHK(c, rocblas_zgemm_strided_batched(
+                   c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, (rocblas_int)N,
+                   (rocblas_int)N, (rocblas_int)chunk, &one, rb(B), (rocblas_int)ld, (rocblas_stride)(chunk * ld),
+                   rb(A), (rocblas_int)ld, (rocblas_stride)(chunk * ld), &zero,
+                   reinterpret_cast<rocblas_double_complex *>(part), (rocblas_int)N, (rocblas_stride)(N * N),
+                   (rocblas_int)nb));
+    int nparts = (int)nb;
+    if (tail > 0) {
+        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose,
+                                 (rocblas_int)N, (rocblas_int)N, (rocblas_int)tail, &one, rb(B + nb * chunk * ld),
+                                 (rocblas_int)ld, rb(A + nb * chunk * ld), (rocblas_int)ld, &zero,
+                                 reinterpret_cast<rocblas_double_complex *>(part + nb * N * N), (rocblas_int)N));
+        ++nparts;
+    }
+    HIPCHK(c, launch_sum_parts(N * N, nparts, part, Sm, s));
+    return CHFSI_OK;
+}
+
+// C = A B for row-major N x N matrices (column-major BLAS computes C^T = B^T A^T)
+int small_mm(chfsi_ctx *c, const cd *A, const cd *B, cd *Cm, int64_t N, bool conjA, hipStream_t s) {
+    BLASCHK(c, rocblas_set_stream(c->blas, s));
+    const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
+    // conjA: C = A^H B, i.e. C^T = B^T conj(A) = (buffer of B) op_C(buffer of A)
+    BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none,
+                             conjA ? rocblas_operation_conjugate_transpose : rocblas_operation_none, (rocblas_int)N,
+                             (rocblas_int)N, (rocblas_int)N, &one, reinterpret_cast<const rocblas_double_complex *>(B),
+                             (rocblas_int)N, reinterpret_cast<const rocblas_double_complex *>(A), (rocblas_int)N,
+                             &zero, reinterpret_cast<rocblas_double_complex *>(Cm), (rocblas_int)N));
     return CHFSI_OK;
 }
 
@@ -372,7 +416,7 @@ int orthonormalize_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64
     const Layout &L = c->L;
     cd *Sm = c->S<cd>(L.small);
     cd *T = Sm + L.small_bytes / sizeof(cd);
-    double *scale = reinterpret_cast<double *>(c->scr + L.small + 7 * L.small_bytes);
+    double *scale = reinterpret_cast<double *>(c->scr + L.small + 9 * L.small_bytes);
     int *flag = c->S<int>(L.flag);
     HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), s));
     for (int pass = 0; pass < 2; ++pass) {
@@ -407,6 +451,45 @@ int rr_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, doubl
     if ((rc = rotate(c, Y, Q, nvec, ld, s))) return rc;
     if ((rc = rotate(c, HY, Q, nvec, ld, s))) return rc;
     if ((rc = rotate(c, MY, Q, nvec, ld, s))) return rc;
+    if (R || resnorm)
+        HIPCHK(c, launch_residual(2 * c->m.M, nvec, ld, HY, MY, ritz, R, c->S<double>(L.red), resnorm, s));
+    return CHFSI_OK;
+}
+
+// Rayleigh-Ritz on a block that is not M-orthonormal (the generalized
+// subspace problem of Algorithm RChFSI, Y^H H Y Q = Y^H M Y Q Lambda):
+// S = Y^H MY, Hs = Y^H HY, s = diag(S)^{-1/2}, L L^H = diag(s) S diag(s),
+// T = diag(s) L^{-H}, C = T^H Hs T, C W = W Lambda, Q = T W,
+// (Y, HY, MY) <- (.) Q.  Two Gram products and three rotations.
+// Returns CHFSI_E_NOT_SPD if the Cholesky factorisation breaks down.
+int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, double *ritz, cd *R,
+                    double *resnorm, hipStream_t s) {
+    const Layout &L = c->L;
+    const size_t st = L.small_bytes / sizeof(cd);
+    cd *Sm = c->S<cd>(L.small), *Hs = Sm + st, *T = Sm + 2 * st, *W = Sm + 3 * st, *Cm = Sm + 4 * st;
+    cd *A2 = Sm + 5 * st, *V = Sm + 6 * st, *V2 = Sm + 7 * st;
+    double *scale = reinterpret_cast<double *>(c->scr + L.small + 9 * L.small_bytes);
+    int *flag = c->S<int>(L.flag);
+    int rc;
+    HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), s));
+    if ((rc = gram(c, Y, MY, nvec, ld, Sm, s))) return rc;
+    if ((rc = gram(c, Y, HY, nvec, ld, Hs, s))) return rc;
+    HIPCHK(c, launch_herm_equilibrate((int)nvec, Sm, scale, flag, s));
+    HIPCHK(c, launch_cholesky((int)nvec, Sm, flag, s));
+    HIPCHK(c, launch_tri_inv_scale((int)nvec, Sm, scale, T, s));
+    int f = 0;
+    if ((rc = read_flag(c, s, &f))) return rc;
+    if (f) return fail(c, CHFSI_E_NOT_SPD, "Cholesky of Y^H M Y broke down: the block is (numerically) rank deficient");
+    if ((rc = small_mm(c, Hs, T, W, nvec, false, s))) return rc;   // W = Hs T
+    if ((rc = small_mm(c, T, W, Cm, nvec, true, s))) return rc;    // C = T^H W
+    HIPCHK(c, launch_hermitize((int)nvec, Cm, s));
+    cd *Q = nullptr;
+    int sweeps = 0;
+    HIPCHK(c, launch_jacobi_eig((int)nvec, Cm, A2, V, V2, ritz, c->S<double>(L.red), 60, s, &sweeps, &Q));
+    if ((rc = small_mm(c, T, Q, W, nvec, false, s))) return rc;    // W = T Q
+    if ((rc = rotate(c, Y, W, nvec, ld, s))) return rc;
+    if ((rc = rotate(c, HY, W, nvec, ld, s))) return rc;
+    if ((rc = rotate(c, MY, W, nvec, ld, s))) return rc;
     if (R || resnorm)
         HIPCHK(c, launch_residual(2 * c->m.M, nvec, ld, HY, MY, ritz, R, c->S<double>(L.red), resnorm, s));
     return CHFSI_OK;
@@ -704,6 +787,17 @@ int chfsi_rayleigh_ritz(chfsi_ctx *c, void *Y, void *HY, void *MY, int64_t nvec,
     return rr_impl(c, (cd *)Y, (cd *)HY, (cd *)MY, nvec, ld, ritz, (cd *)R, resnorm, S(stream));
 }
 
+int chfsi_rayleigh_ritz_general(chfsi_ctx *c, void *Y, void *HY, void *MY, int64_t nvec, int64_t ld, double *ritz,
+                                void *R, double *resnorm, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_block(c, Y, nvec, ld, "Y")) || (rc = check_block(c, HY, nvec, ld, "HY")) ||
+        (rc = check_block(c, MY, nvec, ld, "MY")))
+        return rc;
+    if (!ritz) return fail(c, CHFSI_E_ARG, "ritz is NULL");
+    return rr_general_impl(c, (cd *)Y, (cd *)HY, (cd *)MY, nvec, ld, ritz, (cd *)R, resnorm, S(stream));
+}
+
 int chfsi_residual(chfsi_ctx *c, const void *HX, const void *MX, const double *ritz, void *R, double *resnorm,
                    int64_t nvec, int64_t ld, void *stream) {
     if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
@@ -744,7 +838,7 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
     cd *X = (cd *)Xv, *HX = (cd *)ws, *MX = (cd *)(ws + blk), *R = (cd *)(ws + 2 * blk);
     double *ritz = (double *)(ws + 3 * blk), *res = ritz + nsub;
     double lmax = o->lambda_max;
-    if (o->lanczos_steps > 0) {
+    if (o->lanczos_steps > 0 && !o->resume) {
         if (!v0) return fail(c, CHFSI_E_ARG, "v0 is NULL but lanczos_steps > 0");
         if ((rc = chfsi_estimate_bounds(c, o->lanczos_steps, v0, &lmax, stream))) return rc;
     }
@@ -753,10 +847,12 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
     for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     auto cleanup = [&]() { for (auto &e : ev) hipEventDestroy(e); };
     HIPCHK(c, hipEventRecord(ev[0], s));
-    if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { cleanup(); return rc; }
-    HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
-    if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { cleanup(); return rc; }
-    if ((rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s))) { cleanup(); return rc; }
+    if (!o->resume) {
+        if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { cleanup(); return rc; }
+        HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
+        if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { cleanup(); return rc; }
+        if ((rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s))) { cleanup(); return rc; }
+    }
     std::vector<double> hr(nsub), hritz(nsub), titer;
     double t_filter = 0, t_rr = 0, first_res = -1;
     int it = 0, converged = 0;
@@ -790,8 +886,13 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
         HIPCHK(c, hipEventRecord(ev[2], s));
         if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { status = rc; break; }
         HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
-        if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { status = rc; break; }
-        if ((rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s))) { status = rc; break; }
+        rc = CHFSI_E_NOT_SPD;
+        if (o->rr_mode == 1) rc = rr_general_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s);
+        if (rc == CHFSI_E_NOT_SPD) {
+            if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { status = rc; break; }
+            rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s);
+        }
+        if (rc) { status = rc; break; }
         HIPCHK(c, hipEventRecord(ev[3], s));
         HIPCHK(c, hipEventSynchronize(ev[3]));
         float ms1 = 0, ms2 = 0;
@@ -823,6 +924,40 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
     }
     if (status != CHFSI_OK) return status;
     return converged || o->fixed_iters ? CHFSI_OK : CHFSI_NOT_CONVERGED;
+}
+
+int chfsi_profile_apply_H(chfsi_ctx *c, chfsi_prec prec, const void *X, void *Y, int64_t nvec, int64_t ld,
+                          double ms[3], int *launches, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (prec < CHFSI_FP64 || prec > CHFSI_BF16) return fail(c, CHFSI_E_ARG, "unknown precision");
+    if (!ms) return fail(c, CHFSI_E_ARG, "ms is NULL");
+    int rc;
+    if ((rc = check_block(c, X, nvec, ld, "X")) || (rc = check_block(c, Y, nvec, ld, "Y"))) return rc;
+    if (X == Y) return fail(c, CHFSI_E_ARG, "X and Y must not overlap");
+    hipStream_t s = S(stream);
+    hipEvent_t ev[3];
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    const int nl = c->m.npairs > 0 ? FLAG_NLOC : 0;
+    hipError_t err = hipEventRecord(ev[0], s);
+    if (err == hipSuccess && nl) err = launch_nonlocal_coeffs(c, prec, 0, X, nvec, ld, s);
+    if (err == hipSuccess) err = hipEventRecord(ev[1], s);
+    if (err == hipSuccess) err = launch_cell_op(c, prec, MODE_HAM, nl, 1.0, X, Y, nvec, ld, s);
+    if (err == hipSuccess) err = hipEventRecord(ev[2], s);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+    float a = 0, b = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
+    for (auto &e : ev) hipEventDestroy(e);
+    if (err != hipSuccess) return fail(c, CHFSI_E_DEVICE, std::string("profile failed: ") + hipGetErrorString(err));
+    ms[0] = b;
+    ms[1] = a;
+    ms[2] = a + b;
+    if (launches) {
+        int n = 0;
+        for (int col = 0; col < 8; ++col) n += c->colour_ptr[col + 1] > c->colour_ptr[col];
+        *launches = n;
+    }
+    return CHFSI_OK;
 }
 
 int chfsi_info(const chfsi_ctx *c, int64_t *nnodes, int64_t *ncells, int *n, int *nq) {

@@ -43,6 +43,24 @@ __global__ void equil_apply_kernel(int N, cd *S, const double *scale) {
     S[(int64_t)j * N + i] = h;
 }
 
+// out = sum over the nparts partial matrices, in order
+__global__ void sum_parts_kernel(int64_t n, int nparts, const cd *parts, cd *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = 0, y = 0;
+    for (int p = 0; p < nparts; ++p) {
+        cd v = parts[(int64_t)p * n + i];
+        x += v.x;
+        y += v.y;
+    }
+    out[i] = cd{x, y};
+}
+
+hipError_t launch_sum_parts(int64_t n, int nparts, const cd *parts, cd *out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nparts, parts, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_herm_equilibrate(int N, cd *S, double *scale, int *flag, hipStream_t s) {
     hipLaunchKernelGGL(equil_scale_kernel, dim3((N + 255) / 256), dim3(256), 0, s, N, S, scale, flag);
     int64_t nn = (int64_t)N * N;
@@ -59,8 +77,9 @@ hipError_t launch_hermitize(int N, cd *S, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // in-place Cholesky A = L L^H (lower; the strict upper triangle is zeroed).
-// One workgroup: right-looking, column by column.  flag = 1 on a
-// non-positive pivot.
+// One workgroup: right-looking, column by column.  The matrices factored
+// here are equilibrated to a unit diagonal, so a pivot below 64 eps means
+// the block is numerically rank deficient: flag = 1.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void cholesky_kernel(int N, cd *A, int *flag) {
     __shared__ double djj;
@@ -71,7 +90,7 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int N, cd *A, int *flag)
     for (int j = 0; j < N; ++j) {
         if (tid == 0) {
             double d = A[(int64_t)j * N + j].x;
-            if (!(d > 0.0) || !isfinite(d)) {
+            if (!(d > 64.0 * 2.220446049250313e-16) || !isfinite(d)) {
                 bad = 1;
                 d = 1.0;
             }

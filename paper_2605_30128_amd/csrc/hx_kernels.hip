@@ -1,27 +1,30 @@
-// Matrix-free cell-level Hamiltonian-times-multivector product for gfx950.
+// Matrix-free cell-level Hamiltonian-times-multivector product for gfx950
+// (double and float MFMA; the bfloat16 variant is in hx_bf16.hip).
 //
 // Stages follow the paper's product (Sec. III-C2, stages i-iv): gather of the
 // cell block, dense cell contraction, spin-orbit projector term, assembly.
 // The local cell operator of eq. cellHam is applied in factored form:
-//     Y^(e) = K X^(e) + Phi^T [ w|J| (V_q I + B_q . sigma) ] (Phi X^(e)),
+//     Y^(e) = K X^(e) + Phi^T [ w|J| (V_q I + B_q . sigma) (Phi X^(e)) + w|J| phi d ],
 // with K the reference stiffness (1/2 grad N . grad N, identical for every
-// cell of the uniform mesh) and Phi[q][I] = N_I(x_q).  This is the same
-// 2n x 2n spin-block operator of eq. cellHam (H_scal = K + V-mass, H_Bd =
-// B_d-mass) without storing four n x n matrices per cell.
+// cell of the uniform mesh), Phi[q][I] = N_I(x_q), and the last term the
+// spin-orbit apply P_a(e) d_a written at the quadrature points
+// (P_a(e) = Phi^T diag(w|J|) phi_a, so Phi^T (w|J| phi_a d_a) = P_a(e) d_a).
+// This is the 2n x 2n spin-block operator of eq. cellHam (H_scal = K +
+// V-mass, H_Bd = B_d-mass) without storing four n x n matrices per cell.
 //
-// MFMA tiling.  Every cell block is treated as a GEMM with rows = real
-// columns of the vector block (re/im x spin x vector) and columns = nodes or
-// quadrature points.  One workgroup (4 waves) owns one cell and VB vectors;
-// each wave owns one 16-row tile and a slice of the column tiles.  The
-// gathered block sits in LDS as [node][real column]; the shared tables (K,
-// Phi, Phi^T) are read as MFMA B fragments straight from L2.  The 16x16
-// accumulator layout puts the four real columns (re up, im up, re down, im
-// down) of one vector at one quadrature point into one lane, so the 2x2
+// MFMA tiling.  Every cell block is a GEMM with rows = real columns of the
+// vector block (re/im x spin x vector) and columns = nodes or quadrature
+// points.  One workgroup (4 waves) owns one cell and VB vectors; each wave
+// owns one 16-row tile and a slice of the column tiles.  The gathered block
+// sits in LDS as [node][real column]; the shared tables (K, Phi, Phi^T) are
+// read as MFMA B fragments from L2, one k-step ahead of their use.  The
+// 16x16 accumulator layout puts the four real columns (re up, im up, re down,
+// im down) of one vector at one quadrature point into one lane, so the 2x2
 // spin term is applied in registers.  Assembly is colour-ordered: the eight
 // parity classes of cells are launched one after another, so no two
 // workgroups of a launch touch the same node and no atomics are needed
 // (results are deterministic).
-#include "internal.h"
+#include "cell_common.h"
 
 namespace chfsi {
 
@@ -42,42 +45,6 @@ template <> struct MM<float> {
     }
 };
 
-// Workgroup ids are dealt to the 8 XCDs round robin; map them so that the
-// workgroups of one XCD take a contiguous range of logical tiles (the vector
-// blocks of the same cells share that XCD's L2).
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t total) {
-    int64_t q = total >> 3, r = total & 7;
-    int64_t x = b & 7, i = b >> 3;
-    return x * q + (x < r ? x : r) + i;
-}
-
-struct CellParams {
-    const void *X;
-    void *Y;
-    int64_t ld, nvec;
-    const int *cells;
-    int64_t ncl;
-    int px, py, pz;
-    int64_t ncx, ncy, Nx, Ny, Nz;
-    int p, n1, n;
-    const void *Bk, *BphiT, *Bphi, *W, *dinv;
-    double alpha;
-    const int *cell_pair_ptr, *cell_pairs, *pair_atom;
-    const void *P, *dcoef;
-    int nbeta;
-    int64_t ldd;
-    int mode, flags;
-};
-
-__device__ __forceinline__ int64_t gnode_of(int ijk, int64_t ex, int64_t ey, int64_t ez, int p,
-                                            int64_t Nx, int64_t Ny, int64_t Nz) {
-    int64_t gx = ex * p + (ijk & 255), gy = ey * p + ((ijk >> 8) & 255), gz = ez * p + (ijk >> 16);
-    gx -= gx >= Nx ? Nx : 0;
-    gy -= gy >= Ny ? Ny : 0;
-    gz -= gz >= Nz ? Nz : 0;
-    return gx + Nx * (gy + Ny * gz);
-}
-
 template <typename T> struct LdsPad { static constexpr int v = 4; };
 template <> struct LdsPad<float> { static constexpr int v = 8; };
 
@@ -88,6 +55,10 @@ template <> struct LdsPad<float> { static constexpr int v = 8; };
 // registers 0..3 of lane l in both cases.
 template <typename T> __device__ __forceinline__ constexpr int rcol(int v, int comp) {
     return sizeof(T) == 8 ? 16 * (v >> 2) + 4 * comp + (v & 3) : 4 * v + comp;
+}
+// inverse within a 16-row tile: row r -> (vector in tile, component)
+template <typename T> __device__ __forceinline__ void rinv(int r, int &v, int &comp) {
+    if (sizeof(T) == 8) { v = r & 3; comp = r >> 2; } else { v = r >> 2; comp = r & 3; }
 }
 
 // Gathers the vector block of one cell into LDS as xs[I][rcol(v, 2s + r)].
@@ -117,19 +88,36 @@ __device__ __forceinline__ void gather_block(T *xs, const int *ijk, const void *
 }
 
 // acc[t] += A^T(rows 16m.., k) * B(k, cols (nt0+t)*16..) over k in [0, NP):
-// A from LDS (as[k][c]), B from global ([k][NP] row-major).
-template <typename T, int NTW, int NP, int XS>
+// A from LDS (as[k][c]), B from global ([k][NP] row-major), the B fragments
+// of step k+4 loaded while the MFMAs of step k run.
+template <typename T, int NTW, int NP, int XS, bool PREFETCH = true>
 __device__ __forceinline__ void mfma_panel(typename MM<T>::acc *acc, const T *as, const T *B, int m,
                                            int nt0, int lane) {
     const int kr = lane >> 4, cn = lane & 15;
     const T *bp = B + (size_t)kr * NP + nt0 * 16 + cn;
     const T *ap = as + kr * XS + 16 * m + cn;
-#pragma unroll 2
-    for (int kk = 0; kk < NP; kk += 4) {
-        T av = ap[kk * XS];
-        const T *brow = bp + (size_t)kk * NP;
+    if (!PREFETCH) {
+        for (int kk = 0; kk < NP; kk += 4) {
+            T av = ap[kk * XS];
+            const T *brow = bp + (size_t)kk * NP;
 #pragma unroll
-        for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, brow[16 * t], acc[t]);
+            for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, brow[16 * t], acc[t]);
+        }
+        return;
+    }
+    T bc[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) bc[t] = bp[16 * t];
+    for (int kk = 0; kk < NP; kk += 4) {
+        const int kn = kk + 4 < NP ? kk + 4 : kk;
+        T bn[NTW];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) bn[t] = bp[(size_t)kn * NP + 16 * t];
+        T av = ap[kk * XS];
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, bc[t], acc[t]);
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) bc[t] = bn[t];
     }
 }
 
@@ -184,6 +172,33 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
             tq[t][2] = bx * ur - by * ui + (v - bz) * dr;
             tq[t][3] = bx * ui + by * ur + (v - bz) * di;
         }
+        // spin-orbit apply at the quadrature points: T += w|J| phi_a d_a, as
+        // an MFMA with k = (projector j, spin s', re|im part) and
+        // A[(v, s, r)][(j, s', part)] = delta_{s s'} (re/im part of d_j(v))
+        if ((a.flags & FLAG_NLOC) && a.cell_pair_ptr) {
+            const int pb = a.cell_pair_ptr[e], pe = a.cell_pair_ptr[e + 1];
+            int vr, comp;
+            rinv<T>(lane & 15, vr, comp);
+            const int sA = comp >> 1, rA = comp & 1, kr = lane >> 4, sB = kr >> 1, part = kr & 1;
+            const int64_t colA = vb * VB + 4 * m + vr;
+            const bool act = sA == sB && colA < a.nvec;
+            for (int pp = pb; pp < pe; ++pp) {
+                const int pair = a.cell_pairs[pp];
+                const int atom = a.pair_atom[pair];
+                const T *wp = reinterpret_cast<const T *>(a.P) + (size_t)pair * 4 * a.nbeta * NP;
+                const TC *dc = reinterpret_cast<const TC *>(a.dcoef) + (size_t)atom * a.nbeta * a.ldd;
+                for (int j = 0; j < a.nbeta; ++j) {
+                    T av = 0;
+                    if (act) {
+                        TC d = dc[(size_t)j * a.ldd + colA];
+                        av = rA == 0 ? (part == 0 ? d.x : -d.y) : (part == 0 ? d.y : d.x);
+                    }
+                    const T *brow = wp + (size_t)(4 * j + kr) * NP + nt0 * 16 + (lane & 15);
+#pragma unroll
+                    for (int t = 0; t < NTW; ++t) tq[t] = MM<T>::mma(av, brow[16 * t], tq[t]);
+                }
+            }
+        }
         __syncthreads();  // every wave is done reading the gathered block
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
@@ -194,32 +209,6 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
         }
         __syncthreads();
         mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
-
-        if ((a.flags & FLAG_NLOC) && a.cell_pair_ptr) {
-            const int64_t col = vb * VB + 4 * m + (lane >> 4);
-            const int pb = a.cell_pair_ptr[e], pe = a.cell_pair_ptr[e + 1];
-            if (col < a.nvec) {
-                for (int pp = pb; pp < pe; ++pp) {
-                    const int pair = a.cell_pairs[pp];
-                    const int atom = a.pair_atom[pair];
-                    const TC *P = reinterpret_cast<const TC *>(a.P) + (size_t)pair * NP * 2 * a.nbeta;
-                    const TC *dc = reinterpret_cast<const TC *>(a.dcoef) + (size_t)atom * a.nbeta * a.ldd + col;
-                    for (int j = 0; j < a.nbeta; ++j) {
-                        TC d = dc[(size_t)j * a.ldd];
-#pragma unroll
-                        for (int t = 0; t < NTW; ++t) {
-                            int J = (nt0 + t) * 16 + (lane & 15);
-                            TC p0 = P[(J * 2 + 0) * a.nbeta + j];
-                            TC p1 = P[(J * 2 + 1) * a.nbeta + j];
-                            y[t][0] += p0.x * d.x - p0.y * d.y;
-                            y[t][1] += p0.x * d.y + p0.y * d.x;
-                            y[t][2] += p1.x * d.x - p1.y * d.y;
-                            y[t][3] += p1.x * d.y + p1.y * d.x;
-                        }
-                    }
-                }
-            }
-        }
     }
 
     // colour-ordered assembly
@@ -233,30 +222,23 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
             int J = (nt0 + t) * 16 + (lane & 15);
             if (J < a.n) {
                 int c = ijk[J];
-                int i = c & 255, j = (c >> 8) & 255, k = c >> 16;
                 int64_t g = gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
-                // first colour to reach this node: parity 0 in every face direction
-                bool fx = (i == 0 || i == a.p), fy = (j == 0 || j == a.p), fz = (k == 0 || k == a.p);
-                bool first = !accum && !(fx && a.px) && !(fy && a.py) && !(fz && a.pz);
-                TC *d0 = Y + (2 * g) * a.ld + col;
-                TC *d1 = d0 + a.ld;
-                TC v0, v1;
-                v0.x = al * y[t][0]; v0.y = al * y[t][1];
-                v1.x = al * y[t][2]; v1.y = al * y[t][3];
-                if (!first) {
-                    TC o0 = *d0, o1 = *d1;
-                    v0.x += o0.x; v0.y += o0.y;
-                    v1.x += o1.x; v1.y += o1.y;
-                }
-                *d0 = v0;
-                *d1 = v1;
+                assemble<T, TC>(Y, a.ld, col, c, a.p, a.px, a.py, a.pz, accum, g, al, y[t][0], y[t][1],
+                                y[t][2], y[t][3]);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// nonlocal projection: part[pair][j][col] = sum_{I,s} conj(P[pair][I][s][j]) x[I][s][col]
+// spin-orbit projection: part[pair][j][col] = sum_{I,s} conj(P[pair][I][s][j]) x[I][s][col]
+// as a real GEMM with rows = vectors, k = (node I, component (s, re|im)) and
+// columns = (j, re|im of the result):
+//   B[(I,s,re)][(j,re)] = Re P, B[(I,s,re)][(j,im)] = -Im P,
+//   B[(I,s,im)][(j,re)] = Im P, B[(I,s,im)][(j,im)] = Re P.
+// One workgroup per (cell with projectors, vector block); the four waves
+// split the node range, their partial tiles are summed in LDS in a fixed
+// order.
 // ---------------------------------------------------------------------------
 struct ProjParams {
     const void *X;
@@ -273,62 +255,94 @@ struct ProjParams {
     int flags;
 };
 
-template <typename T, int MT, int NP>
+template <typename T, int VBP, int NP>
 __global__ __launch_bounds__(kThreads) void proj_kernel(ProjParams a) {
     using TC = typename Cplx<T>::type;
-    constexpr int VB = 4 * MT, CB = 16 * MT;
-    constexpr int XS = CB + LdsPad<T>::v;
-    __shared__ T xs[NP * XS];
+    using acc_t = typename MM<T>::acc;
+    __shared__ __attribute__((aligned(16))) T xs[NP * 4 * VBP];  // [I][comp][v]
     __shared__ int ijk[NP];
-    __shared__ TC red[kThreads];
+    __shared__ T red[4][2][256];
 
-    const int64_t nvb = (a.nvec + VB - 1) / VB;
+    const int64_t nvb = (a.nvec + VBP - 1) / VBP;
     const int64_t t_log = xcd_remap(blockIdx.x, a.ncl * nvb);
     const int64_t ci = t_log / nvb, vb = t_log - ci * nvb;
     const int64_t e = a.cells[ci];
     const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int I = tid; I < NP; I += kThreads) {
         int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
         ijk[I] = i | (j << 8) | (k << 16);
     }
     __syncthreads();
-    gather_block<T, VB, NP, XS>(xs, ijk, a.X, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
-                                a.Ny, a.Nz,
-                                (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr);
+    {
+        const TC *X = reinterpret_cast<const TC *>(a.X);
+        const T *dinv = (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr;
+        for (int idx = tid; idx < NP * 2 * VBP; idx += kThreads) {
+            int v = idx % VBP, s = (idx / VBP) & 1, I = idx / (2 * VBP);
+            int64_t col = vb * VBP + v;
+            T re = 0, im = 0;
+            if (I < a.n && col < a.nvec) {
+                int64_t g = gnode_of(ijk[I], ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+                TC z = X[(2 * g + s) * a.ld + col];
+                T sc = dinv ? dinv[g] : T(1);
+                re = z.x * sc;
+                im = z.y * sc;
+            }
+            xs[(4 * I + 2 * s) * VBP + v] = re;
+            xs[(4 * I + 2 * s + 1) * VBP + v] = im;
+        }
+    }
     __syncthreads();
-    const int nout = VB * a.nbeta;
-    const int nsplit = kThreads / nout;
-    const int o = tid % nout, split = tid / nout;
-    const int j = o / VB, v = o % VB;
-    const int64_t col = vb * VB + v;
+    const int kr = lane >> 4, cn = lane & 15;
+    const int sB = kr >> 1, rB = kr & 1;
+    const int nchunk = (a.n + 3) / 4;
+    const int I0 = wave * nchunk, I1 = min(a.n, I0 + nchunk);
+    const int ntile = (2 * a.nbeta + 15) / 16;
     const int pb = a.cell_pair_ptr[e], pe = a.cell_pair_ptr[e + 1];
     for (int pp = pb; pp < pe; ++pp) {
         const int pair = a.cell_pairs[pp];
         const TC *P = reinterpret_cast<const TC *>(a.P) + (size_t)pair * NP * 2 * a.nbeta;
-        TC acc;
-        acc.x = 0; acc.y = 0;
-        if (split < nsplit) {
-            for (int I = split; I < a.n; I += nsplit) {
+        for (int nt = 0; nt < ntile; ++nt) {
+            const int ncol = nt * 16 + cn, j = ncol >> 1, out = ncol & 1;
+            const bool jv = j < a.nbeta;
+            acc_t acc = acc_t{0, 0, 0, 0};
+            // P values of the next PF nodes stay in flight (register ring)
+            constexpr int PF = 16;
+            const TC *pcol = P + sB * a.nbeta + j;
+            TC pbuf[PF];
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    TC pc = P[(I * 2 + s) * a.nbeta + j];
-                    T xr = xs[I * XS + rcol<T>(v, 2 * s)], xi = xs[I * XS + rcol<T>(v, 2 * s + 1)];
-                    acc.x += pc.x * xr + pc.y * xi;
-                    acc.y += pc.x * xi - pc.y * xr;
+            for (int u = 0; u < PF; ++u) {
+                const int I = I0 + u;
+                pbuf[u] = (jv && I < I1) ? pcol[(size_t)I * 2 * a.nbeta] : TC{0, 0};
+            }
+            for (int Ib = I0; Ib < I1; Ib += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int I = Ib + u;
+                    const TC pv = pbuf[u];
+                    const int In = I + PF;
+                    pbuf[u] = (jv && In < I1) ? pcol[(size_t)In * 2 * a.nbeta] : TC{0, 0};
+                    if (I < I1) {
+                        T av = cn < VBP ? xs[(4 * I + kr) * VBP + cn] : T(0);
+                        T bv = rB == 0 ? (out == 0 ? pv.x : -pv.y) : (out == 0 ? pv.y : pv.x);
+                        acc = MM<T>::mma(av, bv, acc);
+                    }
                 }
             }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) red[wave][nt][lane * 4 + i] = acc[i];
         }
-        red[tid] = acc;
         __syncthreads();
-        if (split == 0) {
-            TC s = red[o];
-            for (int k = 1; k < nsplit; ++k) {
-                s.x += red[k * nout + o].x;
-                s.y += red[k * nout + o].y;
-            }
-            if (col < a.nvec)
-                reinterpret_cast<TC *>(a.part)[((size_t)pair * a.nbeta + j) * a.nvec + col] = s;
+        // sum the four node chunks in a fixed order and store
+        for (int o = tid; o < ntile * 256; o += kThreads) {
+            const int nt = o >> 8, li = (o & 255) >> 2, i = o & 3;
+            T s = red[0][nt][o & 255] + red[1][nt][o & 255] + red[2][nt][o & 255] + red[3][nt][o & 255];
+            const int ccol = li & 15, kl = li >> 4;
+            const int v = sizeof(T) == 8 ? 4 * i + kl : 4 * kl + i;  // accumulator row
+            const int ncol = nt * 16 + ccol, j = ncol >> 1, out = ncol & 1;
+            const int64_t col = vb * VBP + v;
+            if (v < VBP && j < a.nbeta && col < a.nvec)
+                reinterpret_cast<T *>(a.part)[(((size_t)pair * a.nbeta + j) * a.nvec + col) * 2 + out] = s;
         }
         __syncthreads();
     }
@@ -407,12 +421,12 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams a) {
         acc_t tx[NTW], tg[NTW];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) { tx[t] = acc_t{0, 0, 0, 0}; tg[t] = acc_t{0, 0, 0, 0}; }
-        mfma_panel<T, NTW, NP, XS>(tx, xs, BphiT, m, nt0, lane);
+        mfma_panel<T, NTW, NP, XS, false>(tx, xs, BphiT, m, nt0, lane);
         __syncthreads();
         gather_block<T, VB, NP, XS>(xs, ijk, a.G, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
                                     a.Ny, a.Nz, nullptr);
         __syncthreads();
-        mfma_panel<T, NTW, NP, XS>(tg, xs, BphiT, m, nt0, lane);
+        mfma_panel<T, NTW, NP, XS, false>(tg, xs, BphiT, m, nt0, lane);
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             double xur = tx[t][0], xui = tx[t][1], xdr = tx[t][2], xdi = tx[t][3];
@@ -508,6 +522,29 @@ __global__ void setup_proj_kernel(const cd *phi, const double *Phi, const double
     P32[idx].x = (float)ar; P32[idx].y = (float)ai;
 }
 
+// w|J| phi at the quadrature points, k = (j, spin, re|im):
+//   WP[pair][k][q] (double, float) and WPb[pair][q][k] (bfloat16, k padded)
+__global__ void setup_wphi_kernel(const cd *phi, const double *wq, double *W64, float *W32, __bf16 *Wb,
+                                  int64_t npairs, int nq, int NP, int nbeta, int kpad) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= npairs * NP * kpad) return;
+    int64_t pair = idx / ((int64_t)NP * kpad);
+    int r = (int)(idx % ((int64_t)NP * kpad));
+    int q = r / kpad, k = r % kpad;
+    double v = 0;
+    if (q < nq && k < 4 * nbeta) {
+        int j = k >> 2, s = (k >> 1) & 1, part = k & 1;
+        cd z = phi[((size_t)pair * nq + q) * 2 * nbeta + s * nbeta + j];
+        v = wq[q] * (part ? z.y : z.x);
+    }
+    Wb[idx] = (__bf16)(float)v;
+    if (k < 4 * nbeta) {
+        size_t o = ((size_t)pair * 4 * nbeta + k) * NP + q;
+        W64[o] = v;
+        W32[o] = (float)v;
+    }
+}
+
 __global__ void cast_table_kernel(const double *src, float *dst, __bf16 *dstb, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -546,11 +583,11 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
     a.alpha = alpha;
     a.mode = mode;
     a.flags = flags;
-    if ((flags & FLAG_NLOC) && m.npairs > 0) {
+    if ((flags & FLAG_NLOC) && m.npairs > 0 && mode == MODE_HAM) {
         a.cell_pair_ptr = c->P<int>(L.cell_pair_ptr);
         a.cell_pairs = c->P<int>(L.cell_pairs);
         a.pair_atom = c->P<int>(L.pair_atom);
-        a.P = dbl ? c->P<char>(L.P64) : c->P<char>(L.P32);
+        a.P = dbl ? c->P<char>(L.WP64) : c->P<char>(L.WP32);
         a.dcoef = c->S<char>(L.dcoef);
         a.nbeta = m.nbeta;
         a.ldd = nvec;
@@ -572,7 +609,7 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
     return hipSuccess;
 }
 
-template <typename T, int MT, int NP>
+template <typename T, int VBP, int NP>
 static hipError_t run_proj(const chfsi_ctx *c, int flags, const void *X, int64_t nvec, int64_t ld,
                            hipStream_t s) {
     const Mesh &m = c->m;
@@ -592,9 +629,8 @@ static hipError_t run_proj(const chfsi_ctx *c, int flags, const void *X, int64_t
     a.part = c->S<char>(L.partial);
     a.nbeta = m.nbeta;
     a.flags = flags;
-    constexpr int VB = 4 * MT;
-    const int64_t nvb = (nvec + VB - 1) / VB;
-    hipLaunchKernelGGL((proj_kernel<T, MT, NP>), dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
+    const int64_t nvb = (nvec + VBP - 1) / VBP;
+    hipLaunchKernelGGL((proj_kernel<T, VBP, NP>), dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int64_t nthr = m.natoms * nvec;
@@ -644,16 +680,18 @@ hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int fla
     if (prec == CHFSI_FP64) {
         CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
     }
+    if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s);
     CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 4, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
 }
 
+// the projection of the bfloat16 path runs in float (complex64 blocks)
 hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags, const void *X,
                                   int64_t nvec, int64_t ld, hipStream_t s) {
     if (c->m.npairs == 0 || c->m.n_nl_cells == 0) return hipSuccess;
     if (prec == CHFSI_FP64) {
-        CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<double, 2, NP>(c, flags, X, nvec, ld, s)));
+        CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<double, 8, NP>(c, flags, X, nvec, ld, s)));
     }
-    CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<float, 4, NP>(c, flags, X, nvec, ld, s)));
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<float, 16, NP>(c, flags, X, nvec, ld, s)));
 }
 
 hipError_t launch_adjoint_fields(const chfsi_ctx *c, chfsi_prec prec, const void *X, const void *G,
@@ -679,6 +717,10 @@ hipError_t launch_setup_projectors(const chfsi_ctx *c, const cd *phi_dev, hipStr
     hipLaunchKernelGGL(setup_proj_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, phi_dev,
                        c->P<double>(c->L.Phi64), c->P<double>(c->L.Wq), c->P<cd>(c->L.P64),
                        c->P<cf>(c->L.P32), m.npairs, m.n, m.nq, m.npad, m.nbeta);
+    const int64_t nw = m.npairs * m.npad * c->L.kpad;
+    hipLaunchKernelGGL(setup_wphi_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, phi_dev,
+                       c->P<double>(c->L.Wq), c->P<double>(c->L.WP64), c->P<float>(c->L.WP32),
+                       c->P<__bf16>(c->L.WPb), m.npairs, m.nq, m.npad, m.nbeta, c->L.kpad);
     return hipGetLastError();
 }
 

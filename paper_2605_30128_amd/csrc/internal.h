@@ -40,6 +40,9 @@ struct Layout {
     size_t cell_pair_ptr, cell_pairs;        // int32 [ncells+1], [npairs]
     size_t pair_atom, atom_pair_ptr;         // int32 [npairs], [natoms+1]
     size_t P64, P32;                         // complex [npairs][npad][2][nbeta]
+    size_t WP64, WP32;                       // real [npairs][4 nbeta][npad]: w|J| phi, k = (j, spin, re|im)
+    size_t WPb;                              // bfloat16 [npairs][npad][kpad]: same, k contiguous
+    int kpad;                                // 4 nbeta rounded up to 32
     size_t delta64;                          // complex128 [natoms][nbeta][nbeta]
     size_t persistent_bytes;
     // scratch
@@ -95,6 +98,8 @@ enum : int {
 // apply the cell operator for all 8 colours: Y (+)= alpha * Op(X)
 hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
                           const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s);
+hipError_t launch_cell_op_bf16(const chfsi_ctx *c, int mode, int flags, double alpha, const void *X,
+                               void *Y, int64_t nvec, int64_t ld, hipStream_t s);
 // nonlocal projection + per-atom reduction with Delta: dcoef = Delta * P^H X
 hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags, const void *X,
                                   int64_t nvec, int64_t ld, hipStream_t s);
@@ -128,6 +133,7 @@ hipError_t launch_dot_real(int64_t n, const cd *a, const cd *b, double *red, dou
 hipError_t launch_axpby(int64_t n, double a, const cd *x, double b, cd *y, hipStream_t s);
 
 // dense (small N x N, row-major complex128)
+hipError_t launch_sum_parts(int64_t n, int nparts, const cd *parts, cd *out, hipStream_t s);
 hipError_t launch_herm_equilibrate(int N, cd *S, double *scale, int *flag, hipStream_t s);
 hipError_t launch_hermitize(int N, cd *S, hipStream_t s);
 hipError_t launch_cholesky(int N, cd *A, int *flag, hipStream_t s);

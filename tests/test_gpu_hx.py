@@ -80,6 +80,25 @@ def test_hx_fp32_tiny(B, tiny):
     assert _rel(Y, ref) < 2e-6, _rel(Y, ref)
 
 
+def test_hx_bf16_tiny(B, tiny):
+    """bfloat16 operands, float accumulation: error at bfloat16 rounding level
+    (2^-9 relative per operand), and really rounded (not a float product)."""
+    p, o = tiny
+    X = synth.random_block(p.ndof, 32, 104)
+    ref = o.apply_H(X)
+    op = B.Chfsi(p, max_nvec=64)
+    Y = op.apply_H(_dev(X, torch.complex64), prec="bf16").cpu().numpy()
+    err = _rel(Y, ref)
+    assert 1e-5 < err < 2e-2, err
+    # ragged columns in bf16
+    Xr = synth.random_block(p.ndof, 21, 107, ld=24)
+    Yd = _dev(np.zeros((p.ndof, 24)), torch.complex64)
+    op.apply_H(_dev(Xr, torch.complex64), prec="bf16", nvec=21, Y=Yd)
+    Yr = Yd.cpu().numpy()
+    assert _rel(Yr[:, :21], o.apply_H(Xr[:, :21])) < 2e-2
+    assert np.all(Yr[:, 21:] == 0)
+
+
 @pytest.mark.parametrize("deg,ncell,soc", [(1, (2, 2, 2), False), (2, (2, 2, 4), True), (3, (2, 2, 2), True),
                                            (5, (2, 2, 2), True), (6, (2, 2, 2), True), (7, (2, 2, 2), False)])
 def test_hx_all_degrees(B, oracle_lib, deg, ncell, soc):

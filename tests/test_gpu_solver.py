@@ -114,13 +114,32 @@ def test_lanczos_parity(B, tiny_state):
     assert abs(lm - s["lmax"]) < 1e-6 * s["lmax"]
 
 
-def test_solve_tiny_fp64_matches_golden(B):
+def test_rr_general_parity(B, tiny_state):
+    """Generalized Rayleigh-Ritz on a non-orthonormal block gives the Ritz
+    values of the same subspace as Cholesky-QR2 + Rayleigh-Ritz (oracle)."""
+    s = tiny_state
+    o = s["o"]
+    X0 = s["X0"].copy()
+    X0[:, 7] *= 1e3  # badly scaled column
+    HX0, MX0 = o.apply_H(X0), o.apply_M(X0)
+    Yr, HYr, MYr = o.orthonormalize(X0, HX0, MX0)
+    _, _, _, ritz_r = o.rayleigh_ritz(Yr, HYr, MYr)
+    op = B.Chfsi(s["p"], max_nvec=40)
+    Y, HY, MY = _dev(X0), _dev(HX0), _dev(MX0)
+    ritz, R, res = op.rayleigh_ritz(Y, HY, MY, general=True)
+    assert np.abs(ritz.cpu().numpy() - ritz_r).max() < 1e-11 * np.abs(ritz_r).max()
+    Yg = Y.cpu().numpy()
+    assert np.abs(Yg.conj().T @ o.apply_M(Yg) - np.eye(40)).max() < 1e-10
+
+
+@pytest.mark.parametrize("rr_mode", [0, 1])
+def test_solve_tiny_fp64_matches_golden(B, rr_mode):
     g = json.load(open(GOLD))
     p = synth.make_config("tiny")
     op = B.Chfsi(p, max_nvec=g["nsub"])
     X = _dev(synth.random_block(p.ndof, g["nsub"], g["x0_seed"]))
     v0 = torch.from_numpy(synth.random_block(p.ndof, 1, g["lanczos_seed"])[:, 0])
-    out = op.solve(X, g["n_wanted"], g["degree"], prec="fp64", tol=1e-10, max_iter=200, v0=v0)
+    out = op.solve(X, g["n_wanted"], g["degree"], prec="fp64", tol=1e-10, max_iter=200, v0=v0, rr_mode=rr_mode)
     assert out["converged"], out
     ref = np.asarray(g["eigenvalues"][:g["n_wanted"]])
     assert np.abs(out["eigvals"] - ref).max() < 1e-10, np.abs(out["eigvals"] - ref).max()
