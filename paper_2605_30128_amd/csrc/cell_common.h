@@ -43,28 +43,13 @@ __device__ __forceinline__ int64_t gnode_of(int ijk, int64_t ex, int64_t ey, int
     return gx + Nx * (gy + Ny * gz);
 }
 
-// Colour-ordered assembly of one lane's four components (re up, im up, re
-// down, im down) of vector `col` at local node J: the first colour to reach
-// a node (parity 0 in every direction in which the node lies on a cell
-// face) writes, later colours add.  With FLAG_ACCUM every colour adds.
-template <typename T, typename TC>
-__device__ __forceinline__ void assemble(TC *Y, int64_t ld, int64_t col, int c, int p, int px, int py,
-                                         int pz, bool accum, int64_t g, T al, T y0, T y1, T y2, T y3) {
+// Colour-ordered assembly: the first colour to reach a node (parity 0 in
+// every direction in which the node lies on a cell face) writes the node,
+// later colours add to it.  With FLAG_ACCUM every colour adds.
+__device__ __forceinline__ bool first_touch(int c, int p, int px, int py, int pz, bool accum) {
     int i = c & 255, j = (c >> 8) & 255, k = c >> 16;
     bool fx = (i == 0 || i == p), fy = (j == 0 || j == p), fz = (k == 0 || k == p);
-    bool first = !accum && !(fx && px) && !(fy && py) && !(fz && pz);
-    TC *d0 = Y + (2 * g) * ld + col;
-    TC *d1 = d0 + ld;
-    TC v0, v1;
-    v0.x = al * y0; v0.y = al * y1;
-    v1.x = al * y2; v1.y = al * y3;
-    if (!first) {
-        TC o0 = *d0, o1 = *d1;
-        v0.x += o0.x; v0.y += o0.y;
-        v1.x += o1.x; v1.y += o1.y;
-    }
-    *d0 = v0;
-    *d1 = v1;
+    return !accum && !(fx && px) && !(fy && py) && !(fz && pz);
 }
 
 }  // namespace chfsi

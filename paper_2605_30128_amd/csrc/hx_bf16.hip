@@ -70,19 +70,31 @@ __global__ __launch_bounds__(kThreads) void cell_kernel_bf16(CellParams a) {
     {
         const cf *X = reinterpret_cast<const cf *>(a.X);
         const float *dinv = (a.flags & FLAG_DINV) ? reinterpret_cast<const float *>(a.dinv) : nullptr;
-        for (int idx = tid; idx < NP * 2 * VB; idx += kThreads) {
-            int v = idx % VB, s = (idx / VB) & 1, I = idx / (2 * VB);
-            int64_t col = vb * VB + v;
-            float re = 0, im = 0;
-            if (I < a.n && col < a.nvec) {
-                int64_t g = gnode_of(ijk[I], ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
-                cf z = X[(2 * g + s) * a.ld + col];
-                float sc = dinv ? dinv[g] : 1.0f;
-                re = z.x * sc;
-                im = z.y * sc;
+        constexpr int TOT = NP * 2 * VB, ITER = (TOT + kThreads - 1) / kThreads;
+        // all loads of this thread are issued before the first LDS store
+        cf z[ITER];
+        float sc[ITER];
+#pragma unroll
+        for (int u = 0; u < ITER; ++u) {
+            const int idx = tid + u * kThreads;
+            const int v = idx % VB, s = (idx / VB) & 1, I = idx / (2 * VB);
+            const int64_t col = vb * VB + v;
+            z[u] = cf{0.f, 0.f};
+            sc[u] = 1.0f;
+            if (idx < TOT && I < a.n && col < a.nvec) {
+                const int64_t g = gnode_of(ijk[I], ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+                z[u] = X[(2 * g + s) * a.ld + col];
+                if (dinv) sc[u] = dinv[g];
             }
-            xs[(4 * v + 2 * s) * KS + I] = (__bf16)re;
-            xs[(4 * v + 2 * s + 1) * KS + I] = (__bf16)im;
+        }
+#pragma unroll
+        for (int u = 0; u < ITER; ++u) {
+            const int idx = tid + u * kThreads;
+            const int v = idx % VB, s = (idx / VB) & 1, I = idx / (2 * VB);
+            if (idx < TOT) {
+                xs[(4 * v + 2 * s) * KS + I] = (__bf16)(z[u].x * sc[u]);
+                xs[(4 * v + 2 * s + 1) * KS + I] = (__bf16)(z[u].y * sc[u]);
+            }
         }
     }
     __syncthreads();
@@ -169,22 +181,41 @@ __global__ __launch_bounds__(kThreads) void cell_kernel_bf16(CellParams a) {
     }
     panel_bf16<NP, NTW, KS>(y, xs, reinterpret_cast<const __bf16 *>(a.Bphi), mh, nt0, lane);
 
+    // colour-ordered assembly: all previous values of the lane's nodes are
+    // loaded before any is written back
     cf *Y = reinterpret_cast<cf *>(a.Y);
     const float al = (float)a.alpha;
     const bool accum = (a.flags & FLAG_ACCUM) != 0;
+    const int64_t col0 = vb * VB + 4 * (2 * mh) + (lane >> 4), col1 = col0 + 4;
+    int64_t off[NTW];
+    cf o[2][NTW][2];
 #pragma unroll
-    for (int mm = 0; mm < 2; ++mm) {
-        const int64_t col = vb * VB + 4 * (2 * mh + mm) + (lane >> 4);
-        if (col >= a.nvec) continue;
+    for (int t = 0; t < NTW; ++t) {
+        const int J = (nt0 + t) * 16 + (lane & 15);
+        off[t] = -1;
 #pragma unroll
-        for (int t = 0; t < NTW; ++t) {
-            int J = (nt0 + t) * 16 + (lane & 15);
-            if (J < a.n) {
-                int c = ijk[J];
-                int64_t g = gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
-                assemble<float, cf>(Y, a.ld, col, c, a.p, a.px, a.py, a.pz, accum, g, al, y[mm][t][0],
-                                    y[mm][t][1], y[mm][t][2], y[mm][t][3]);
+        for (int mm = 0; mm < 2; ++mm) { o[mm][t][0] = cf{0.f, 0.f}; o[mm][t][1] = cf{0.f, 0.f}; }
+        if (J < a.n) {
+            const int c = ijk[J];
+            off[t] = (2 * gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz)) * a.ld;
+            if (!first_touch(c, a.p, a.px, a.py, a.pz, accum)) {
+                if (col0 < a.nvec) { o[0][t][0] = Y[off[t] + col0]; o[0][t][1] = Y[off[t] + a.ld + col0]; }
+                if (col1 < a.nvec) { o[1][t][0] = Y[off[t] + col1]; o[1][t][1] = Y[off[t] + a.ld + col1]; }
             }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        if (off[t] < 0) continue;
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            const int64_t col = mm ? col1 : col0;
+            if (col >= a.nvec) continue;
+            cf v0, v1;
+            v0.x = al * y[mm][t][0] + o[mm][t][0].x; v0.y = al * y[mm][t][1] + o[mm][t][0].y;
+            v1.x = al * y[mm][t][2] + o[mm][t][1].x; v1.y = al * y[mm][t][3] + o[mm][t][1].y;
+            Y[off[t] + col] = v0;
+            Y[off[t] + a.ld + col] = v1;
         }
     }
 }

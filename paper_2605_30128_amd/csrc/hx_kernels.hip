@@ -69,21 +69,31 @@ __device__ __forceinline__ void gather_block(T *xs, const int *ijk, const void *
                                              int64_t Ny, int64_t Nz, const T *dinv) {
     using TC = typename Cplx<T>::type;
     const TC *X = reinterpret_cast<const TC *>(Xv);
-    for (int idx = threadIdx.x; idx < NP * 2 * VB; idx += kThreads) {
-        int v = idx % VB;
-        int s = (idx / VB) & 1;
-        int I = idx / (2 * VB);
-        int64_t col = col0 + v;
-        T re = 0, im = 0;
-        if (I < n && col < nvec) {
-            int64_t g = gnode_of(ijk[I], ex, ey, ez, p, Nx, Ny, Nz);
-            TC z = X[(2 * g + s) * ld + col];
-            T sc = dinv ? dinv[g] : T(1);
-            re = z.x * sc;
-            im = z.y * sc;
+    constexpr int TOT = NP * 2 * VB, ITER = (TOT + kThreads - 1) / kThreads;
+    // all loads of this thread are issued before the first LDS store
+    TC z[ITER];
+    T sc[ITER];
+#pragma unroll
+    for (int u = 0; u < ITER; ++u) {
+        const int idx = threadIdx.x + u * kThreads;
+        const int v = idx % VB, s = (idx / VB) & 1, I = idx / (2 * VB);
+        const int64_t col = col0 + v;
+        z[u] = TC{0, 0};
+        sc[u] = T(1);
+        if (idx < TOT && I < n && col < nvec) {
+            const int64_t g = gnode_of(ijk[I], ex, ey, ez, p, Nx, Ny, Nz);
+            z[u] = X[(2 * g + s) * ld + col];
+            if (dinv) sc[u] = dinv[g];
         }
-        xs[I * XS + rcol<T>(v, 2 * s)] = re;
-        xs[I * XS + rcol<T>(v, 2 * s + 1)] = im;
+    }
+#pragma unroll
+    for (int u = 0; u < ITER; ++u) {
+        const int idx = threadIdx.x + u * kThreads;
+        const int v = idx % VB, s = (idx / VB) & 1, I = idx / (2 * VB);
+        if (idx < TOT) {
+            xs[I * XS + rcol<T>(v, 2 * s)] = z[u].x * sc[u];
+            xs[I * XS + rcol<T>(v, 2 * s + 1)] = z[u].y * sc[u];
+        }
     }
 }
 
@@ -211,20 +221,38 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
         mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
     }
 
-    // colour-ordered assembly
+    // colour-ordered assembly: the previous values of all the lane's nodes
+    // are loaded before any is written back
     TC *Y = reinterpret_cast<TC *>(a.Y);
     const int64_t col = vb * VB + 4 * m + (lane >> 4);
     if (col < a.nvec) {
         const T al = (T)a.alpha;
         const bool accum = (a.flags & FLAG_ACCUM) != 0;
+        int64_t off[NTW];
+        TC o0[NTW], o1[NTW];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
-            int J = (nt0 + t) * 16 + (lane & 15);
+            const int J = (nt0 + t) * 16 + (lane & 15);
+            off[t] = -1;
+            o0[t] = TC{0, 0};
+            o1[t] = TC{0, 0};
             if (J < a.n) {
-                int c = ijk[J];
-                int64_t g = gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
-                assemble<T, TC>(Y, a.ld, col, c, a.p, a.px, a.py, a.pz, accum, g, al, y[t][0], y[t][1],
-                                y[t][2], y[t][3]);
+                const int c = ijk[J];
+                off[t] = (2 * gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz)) * a.ld + col;
+                if (!first_touch(c, a.p, a.px, a.py, a.pz, accum)) {
+                    o0[t] = Y[off[t]];
+                    o1[t] = Y[off[t] + a.ld];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+            if (off[t] >= 0) {
+                TC v0, v1;
+                v0.x = al * y[t][0] + o0[t].x; v0.y = al * y[t][1] + o0[t].y;
+                v1.x = al * y[t][2] + o1[t].x; v1.y = al * y[t][3] + o1[t].y;
+                Y[off[t]] = v0;
+                Y[off[t] + a.ld] = v1;
             }
         }
     }
@@ -277,19 +305,30 @@ __global__ __launch_bounds__(kThreads) void proj_kernel(ProjParams a) {
     {
         const TC *X = reinterpret_cast<const TC *>(a.X);
         const T *dinv = (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr;
-        for (int idx = tid; idx < NP * 2 * VBP; idx += kThreads) {
-            int v = idx % VBP, s = (idx / VBP) & 1, I = idx / (2 * VBP);
-            int64_t col = vb * VBP + v;
-            T re = 0, im = 0;
-            if (I < a.n && col < a.nvec) {
-                int64_t g = gnode_of(ijk[I], ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
-                TC z = X[(2 * g + s) * a.ld + col];
-                T sc = dinv ? dinv[g] : T(1);
-                re = z.x * sc;
-                im = z.y * sc;
+        constexpr int TOT = NP * 2 * VBP, ITER = (TOT + kThreads - 1) / kThreads;
+        TC z[ITER];
+        T sc[ITER];
+#pragma unroll
+        for (int u = 0; u < ITER; ++u) {
+            const int idx = tid + u * kThreads;
+            const int v = idx % VBP, s = (idx / VBP) & 1, I = idx / (2 * VBP);
+            const int64_t col = vb * VBP + v;
+            z[u] = TC{0, 0};
+            sc[u] = T(1);
+            if (idx < TOT && I < a.n && col < a.nvec) {
+                const int64_t g = gnode_of(ijk[I], ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+                z[u] = X[(2 * g + s) * a.ld + col];
+                if (dinv) sc[u] = dinv[g];
             }
-            xs[(4 * I + 2 * s) * VBP + v] = re;
-            xs[(4 * I + 2 * s + 1) * VBP + v] = im;
+        }
+#pragma unroll
+        for (int u = 0; u < ITER; ++u) {
+            const int idx = tid + u * kThreads;
+            const int v = idx % VBP, s = (idx / VBP) & 1, I = idx / (2 * VBP);
+            if (idx < TOT) {
+                xs[(4 * I + 2 * s) * VBP + v] = z[u].x * sc[u];
+                xs[(4 * I + 2 * s + 1) * VBP + v] = z[u].y * sc[u];
+            }
         }
     }
     __syncthreads();
