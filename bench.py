@@ -58,6 +58,48 @@ def cpu_baseline(p, nvec=4):
                       f"projector tables included, {dt:.1f} s"}
 
 
+def converge(op, p, cfg, precs, tol, max_iter, seed=7002):
+    """Runs Algorithm RChFSI to the tolerance in each precision from the same
+    start block, one iteration per library call so that progress is printed,
+    and compares the wanted eigenvalues with the FP64 run."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30128_amd import synth
+    nsub, q, nw = cfg["nsub"], cfg["cheb_degree"], cfg["n_wanted"]
+    X0 = synth.random_block(p.ndof, nsub, seed)
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, seed + 1)[:, 0])
+    res = {}
+    for prec in precs:
+        X = torch.from_numpy(X0).to("cuda", torch.complex128)
+        t0 = time.perf_counter()
+        out = op.solve(X, nw, q, prec=prec, tol=tol, max_iter=1, v0=v0)
+        lmax, work, hist = out["bounds"][2], out["work"], [float(out["hist_res"][0])]
+        it = 1
+        while not out["converged"] and it < max_iter:
+            out = op.solve(X, nw, q, prec=prec, tol=tol, max_iter=1, resume=True, work=work, lambda_max=lmax)
+            hist.append(float(out["max_res"]))
+            it += 1
+            log(f"[converge] {prec} iteration {it}: max residual {out['max_res']:.3e} "
+                f"({time.perf_counter() - t0:.0f}s)")
+        torch.cuda.synchronize()
+        res[prec] = dict(iters=it, converged=bool(out["converged"]), seconds=time.perf_counter() - t0,
+                         eig=out["eigvals"].copy(), hist=hist)
+        log(f"[converge] {prec}: {it} iterations, converged={out['converged']}, {res[prec]['seconds']:.1f}s")
+        del X
+        torch.cuda.empty_cache()
+    summary = {"tol": tol, "n_wanted": nw, "nsub": nsub, "degree": q}
+    for prec in precs:
+        r = res[prec]
+        d = {"iterations": r["iters"], "converged": r["converged"], "seconds": r["seconds"],
+             "residual_history": r["hist"]}
+        if prec != "fp64" and "fp64" in res:
+            d["max_abs_eig_diff_vs_fp64"] = float(np.abs(r["eig"] - res["fp64"]["eig"]).max())
+        summary[prec] = d
+    summary["eig_fp64_first8"] = res["fp64"]["eig"][:8].tolist() if "fp64" in res else None
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +110,10 @@ def main():
     ap.add_argument("--hx-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-iter", action="store_true")
+    ap.add_argument("--converge", action="store_true",
+                    help="instead of timing: solve to --tol in fp64, bf16 and fp32 and compare eigenvalues")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-iter", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
@@ -89,6 +135,10 @@ def main():
     nsub, nhx, q = cfg["nsub"], cfg["nvec_hx"], cfg["cheb_degree"]
     op = binding.Chfsi(p, max_nvec=max(nsub, nhx))
     log("[bench] setup done")
+    if args.converge:
+        print(json.dumps({"convergence": converge(op, p, cfg, ["fp64", "bf16", "fp32"], args.tol, args.max_iter)}),
+              flush=True)
+        return
 
     # ---- isolated H X per precision (nhx vectors)
     hx = {}
