@@ -114,6 +114,10 @@ def main():
                     help="instead of timing: solve to --tol in fp64, bf16 and fp32 and compare eigenvalues")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--hx-only", action="store_true",
+                    help="only the H X products (for counter runs) and a 1 GiB device copy that calibrates "
+                         "the memory counters")
+    ap.add_argument("--hx-precs", default="fp64,fp32,bf16")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
@@ -140,10 +144,19 @@ def main():
               flush=True)
         return
 
+    if args.hx_only:
+        # a plain copy of 1 GiB: reads and writes 2^30 bytes each
+        a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     # ---- isolated H X per precision (nhx vectors)
     hx = {}
     prof = {}
-    for prec in ("fp64", "fp32", "bf16"):
+    for prec in args.hx_precs.split(","):
         dt = torch.complex128 if prec == "fp64" else torch.complex64
         X = torch.from_numpy(synth.random_block(p.ndof, nhx, 7001)).to("cuda", dt)
         Y = torch.empty_like(X)
@@ -160,6 +173,9 @@ def main():
         log(f"[bench] H X {prec}: {tot:.2f} ms ({cell:.2f} cell, {coef:.2f} coeff) -> {hx[prec]:.2f} GDoF*vec/s")
         del X, Y
     torch.cuda.empty_cache()
+    if args.hx_only:
+        print(json.dumps({"hx_gdofvec_per_s": hx, "hx_profile_ms": prof}), flush=True)
+        return
 
     # ---- the timed steps: R-ChFSI iterations
     n_wanted = cfg["n_wanted"]

@@ -203,8 +203,9 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
     L.cell_pairs = take((size_t)std::max<int64_t>(m.npairs, 1) * 4);
     L.pair_atom = take((size_t)std::max<int64_t>(m.npairs, 1) * 4);
     L.atom_pair_ptr = take((size_t)(m.natoms + 1) * 4);
-    L.P64 = take((size_t)m.npairs * m.npad * 2 * m.nbeta * 16);
-    L.P32 = take((size_t)m.npairs * m.npad * 2 * m.nbeta * 8);
+    // projection tables [pair][tile of 8 projectors][node][j % 8][spin]
+    L.P64 = take((size_t)m.npairs * ((m.nbeta + 7) / 8) * m.npad * 16 * 16);
+    L.P32 = take((size_t)m.npairs * ((m.nbeta + 7) / 8) * m.npad * 16 * 8);
     L.kpad = (4 * m.nbeta + 31) / 32 * 32;
     L.WP64 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 8);
     L.WP32 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 4);
@@ -518,12 +519,11 @@ int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds,
     for (int k = 1; k < degree; ++k) {
         const double sn = 1.0 / (2.0 / s1 - sk);
         const double a = 2.0 * sn / e;
-        // Z_{k+1} = -a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k
-        HIPCHK(c, launch_filter_init_ld(rows, nvec, nvec, ld, z32, Zn, Zc, k > 1 ? Zp : nullptr, R, -a * cc,
-                                        -sk * sn, lamk + (int64_t)k * nvec, a, s));
-        // Z_{k+1} += a H D^{-1} Z_k
+        // Z_{k+1} = a H D^{-1} Z_k - a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k: the
+        // recurrence terms are added by the cell kernel where it first writes a node
         if (nl) HIPCHK(c, launch_nonlocal_coeffs(c, prec, FLAG_DINV, Zc, nvec, nvec, s));
-        HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_ACCUM | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s));
+        const InitTerms it{Zc, k > 1 ? Zp : nullptr, R, ld, -a * cc, -sk * sn, a, lamk + (int64_t)k * nvec};
+        HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_INIT | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s, &it));
         void *t = Zp; Zp = Zc; Zc = Zn; Zn = t;
         sk = sn;
     }

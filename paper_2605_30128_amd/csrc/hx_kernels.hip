@@ -131,6 +131,75 @@ __device__ __forceinline__ void mfma_panel(typename MM<T>::acc *acc, const T *as
     }
 }
 
+// The shared table of a panel staged through LDS in slices of KS rows of
+// its [k][NP] layout (a slice is contiguous in memory, so it is fetched with
+// 16-byte loads by all 256 threads), double buffered: the next slice is in
+// flight in registers while the MFMAs of the current one run.  Each table
+// byte then crosses L2 once per workgroup instead of once per wave.  Rows
+// are padded so that the four k rows a wave reads per MFMA fall on disjoint
+// LDS banks.
+template <typename T, int NP> struct Stage {
+    static constexpr int KS = sizeof(T) == 8 ? 8 : 16;
+    static constexpr int PAD = sizeof(T) == 8 ? 16 : (16 - NP % 64 + 64) % 64;
+    static constexpr int BS = NP + PAD;
+    static constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
+    static constexpr int CH = KS * NP / EPC;
+    static constexpr int IT = (CH + kThreads - 1) / kThreads;
+    static constexpr int NS = NP / KS;
+    static constexpr size_t bytes = 2 * (size_t)KS * BS * sizeof(T);
+};
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int NP>
+__device__ __forceinline__ void stage_load(u4 *r, const T *B, int k0) {
+    using S = Stage<T, NP>;
+    const u4 *src = reinterpret_cast<const u4 *>(B + (size_t)k0 * NP);
+#pragma unroll
+    for (int u = 0; u < S::IT; ++u) {
+        const int c = threadIdx.x + u * kThreads;
+        if (c < S::CH) r[u] = src[c];
+    }
+}
+template <typename T, int NP>
+__device__ __forceinline__ void stage_store(const u4 *r, T *bs) {
+    using S = Stage<T, NP>;
+#pragma unroll
+    for (int u = 0; u < S::IT; ++u) {
+        const int c = threadIdx.x + u * kThreads;
+        if (c < S::CH) {
+            const int e = c * S::EPC, row = e / NP, col = e - row * NP;
+            *reinterpret_cast<u4 *>(bs + row * S::BS + col) = r[u];
+        }
+    }
+}
+
+// as mfma_panel, with B read from LDS slices; all threads of the workgroup
+// must call it (it contains barriers) and it ends with a barrier
+template <typename T, int NTW, int NP, int XS>
+__device__ __forceinline__ void mfma_panel_staged(typename MM<T>::acc *acc, const T *as, const T *B, T *bs,
+                                                  int m, int nt0, int lane) {
+    using S = Stage<T, NP>;
+    const int kr = lane >> 4, cn = lane & 15;
+    u4 r[S::IT];
+    stage_load<T, NP>(r, B, 0);
+    stage_store<T, NP>(r, bs);
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < S::NS; ++s) {
+        const T *cur = bs + (s & 1) * S::KS * S::BS + kr * S::BS + nt0 * 16 + cn;
+        if (s + 1 < S::NS) stage_load<T, NP>(r, B, (s + 1) * S::KS);
+        const T *ap = as + (s * S::KS + kr) * XS + 16 * m + cn;
+#pragma unroll
+        for (int kk = 0; kk < S::KS; kk += 4) {
+            const T av = ap[kk * XS];
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, cur[kk * S::BS + 16 * t], acc[t]);
+        }
+        if (s + 1 < S::NS) stage_store<T, NP>(r, bs + ((s + 1) & 1) * S::KS * S::BS);
+        __syncthreads();
+    }
+}
+
 template <typename T, int MT, int NP>
 __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
     using TC = typename Cplx<T>::type;
@@ -139,7 +208,10 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
     constexpr int XS = CB + LdsPad<T>::v;
     constexpr int NT = NP / 16, WN = 4 / MT, NTW = NT / WN;
     static_assert(NT % WN == 0, "tile split");
+    // stage the tables through LDS where the block leaves room for two slices
+    constexpr bool STAGED = NP * XS * sizeof(T) + Stage<T, NP>::bytes + NP * sizeof(int) <= 158 * 1024;
     __shared__ __attribute__((aligned(16))) T xs[NP * XS];
+    __shared__ __attribute__((aligned(16))) T bs[STAGED ? Stage<T, NP>::bytes / sizeof(T) : 1];
     __shared__ int ijk[NP];
 
     const int64_t nvb = (a.nvec + VB - 1) / VB;
@@ -163,13 +235,19 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
     acc_t y[NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) y[t] = acc_t{0, 0, 0, 0};
-    mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bk), m, nt0, lane);
+    if constexpr (STAGED)
+        mfma_panel_staged<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bk), bs, m, nt0, lane);
+    else
+        mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bk), m, nt0, lane);
 
     if (a.mode == MODE_HAM) {
         acc_t tq[NTW];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) tq[t] = acc_t{0, 0, 0, 0};
-        mfma_panel<T, NTW, NP, XS>(tq, xs, reinterpret_cast<const T *>(a.BphiT), m, nt0, lane);
+        if constexpr (STAGED)
+            mfma_panel_staged<T, NTW, NP, XS>(tq, xs, reinterpret_cast<const T *>(a.BphiT), bs, m, nt0, lane);
+        else
+            mfma_panel<T, NTW, NP, XS>(tq, xs, reinterpret_cast<const T *>(a.BphiT), m, nt0, lane);
         // pointwise (V + B.sigma) w|J| on (re up, im up, re down, im down)
         const T *W = reinterpret_cast<const T *>(a.W) + (size_t)e * NP * 4;
 #pragma unroll
@@ -218,7 +296,10 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
             for (int i = 0; i < 4; ++i) xs[q * XS + rcol<T>(vl, i)] = tq[t][i];
         }
         __syncthreads();
-        mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
+        if constexpr (STAGED)
+            mfma_panel_staged<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), bs, m, nt0, lane);
+        else
+            mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
     }
 
     // colour-ordered assembly: the previous values of all the lane's nodes
@@ -227,7 +308,7 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
     const int64_t col = vb * VB + 4 * m + (lane >> 4);
     if (col < a.nvec) {
         const T al = (T)a.alpha;
-        const bool accum = (a.flags & FLAG_ACCUM) != 0;
+        const bool accum = (a.flags & FLAG_ACCUM) != 0, init = (a.flags & FLAG_INIT) != 0;
         int64_t off[NTW];
         TC o0[NTW], o1[NTW];
 #pragma unroll
@@ -238,10 +319,14 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
             o1[t] = TC{0, 0};
             if (J < a.n) {
                 const int c = ijk[J];
-                off[t] = (2 * gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz)) * a.ld + col;
+                const int64_t row = 2 * gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+                off[t] = row * a.ld + col;
                 if (!first_touch(c, a.p, a.px, a.py, a.pz, accum)) {
                     o0[t] = Y[off[t]];
                     o1[t] = Y[off[t] + a.ld];
+                } else if (init) {
+                    o0[t] = init_terms<TC>(a, row, off[t], col);
+                    o1[t] = init_terms<TC>(a, row + 1, off[t] + a.ld, col);
                 }
             }
         }
@@ -260,13 +345,19 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
 
 // ---------------------------------------------------------------------------
 // spin-orbit projection: part[pair][j][col] = sum_{I,s} conj(P[pair][I][s][j]) x[I][s][col]
-// as a real GEMM with rows = vectors, k = (node I, component (s, re|im)) and
-// columns = (j, re|im of the result):
-//   B[(I,s,re)][(j,re)] = Re P, B[(I,s,re)][(j,im)] = -Im P,
-//   B[(I,s,im)][(j,re)] = Im P, B[(I,s,im)][(j,im)] = Re P.
-// One workgroup per (cell with projectors, vector block); the four waves
-// split the node range, their partial tiles are summed in LDS in a fixed
-// order.
+// (x = D^-1 z when FLAG_DINV).  One 16x16x4 MFMA contracts four nodes of one
+// component c = (spin, re|im): rows = 16 vectors, k = node, columns =
+// (projector j of an 8-wide tile, re|im of the result), with
+//   B_(s,re)[I][(j,re)] = Re P, B_(s,re)[I][(j,im)] = -Im P,
+//   B_(s,im)[I][(j,re)] = Im P, B_(s,im)[I][(j,im)] = Re P.
+// Both operands come straight from memory into registers: lane (k, m) loads
+// x of node 4g+k, vector m (both spins), and the two spin values of
+// P[I][.][j] from the table laid out [pair][tile][I][j%8][spin], which is
+// zero for padded nodes and projectors.  Nothing is staged in LDS except
+// the cell's node numbers and D^-1 values, so occupancy is limited only by
+// registers and many waves hide the gather latency.  One wave owns
+// (cell, 16 vectors) and walks all nodes for up to four (pair, tile) units
+// at once, so no cross-wave reduction is needed.
 // ---------------------------------------------------------------------------
 struct ProjParams {
     const void *X;
@@ -274,116 +365,106 @@ struct ProjParams {
     const int *cells;  // cells with at least one pair
     int64_t ncl;
     int64_t ncx, ncy, Nx, Ny, Nz;
-    int p, n1, n;
+    int p, n1, n, npad;
     const void *dinv;
     const int *cell_pair_ptr, *cell_pairs;
     const void *P;
     void *part;
-    int nbeta;
+    int nbeta, ntile;
     int flags;
 };
 
-template <typename T, int VBP, int NP>
-__global__ __launch_bounds__(kThreads) void proj_kernel(ProjParams a) {
+constexpr int kProjMaxUnits = 4;   // (pair, tile) units per pass over the nodes
+constexpr int kProjMaxNodes = 512; // (p+1)^3 for p <= 7
+
+template <typename T, int NB>
+__device__ __forceinline__ void proj_pass(const ProjParams &a, const int *gtab, const T *sc, int64_t vb16,
+                                          int u0, int pb, int lane) {
     using TC = typename Cplx<T>::type;
     using acc_t = typename MM<T>::acc;
-    __shared__ __attribute__((aligned(16))) T xs[NP * 4 * VBP];  // [I][comp][v]
-    __shared__ int ijk[NP];
-    __shared__ T red[4][2][256];
+    const int k = lane >> 4, m = lane & 15, jj = m >> 1;
+    const bool odd = m & 1;
+    const int64_t col = vb16 + m;
+    const bool cv = col < a.nvec;
+    const TC *X = reinterpret_cast<const TC *>(a.X);
+    const TC *Q[NB];
+    int pair[NB], tile[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        pair[u] = a.cell_pairs[pb + (u0 + u) / a.ntile];
+        tile[u] = (u0 + u) % a.ntile;
+        Q[u] = reinterpret_cast<const TC *>(a.P) +
+               (((size_t)pair[u] * a.ntile + tile[u]) * a.npad + k) * 16 + 2 * jj;
+    }
+    acc_t acc[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) acc[u] = acc_t{0, 0, 0, 0};
+    const int ngroups = (a.n + 3) >> 2;
+#pragma unroll 2
+    for (int g = 0; g < ngroups; ++g) {
+        const int I = 4 * g + k;
+        TC xu{0, 0}, xd{0, 0};
+        if (cv && I < a.n) {
+            const int64_t r = 2 * (int64_t)gtab[I] * a.ld + col;
+            xu = X[r];
+            xd = X[r + a.ld];
+            const T f = sc[I];
+            xu.x *= f; xu.y *= f; xd.x *= f; xd.y *= f;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const TC pu = Q[u][(size_t)g * 64], pd = Q[u][(size_t)g * 64 + 1];
+            acc[u] = MM<T>::mma(xu.x, odd ? -pu.y : pu.x, acc[u]);
+            acc[u] = MM<T>::mma(xu.y, odd ? pu.x : pu.y, acc[u]);
+            acc[u] = MM<T>::mma(xd.x, odd ? -pd.y : pd.x, acc[u]);
+            acc[u] = MM<T>::mma(xd.y, odd ? pd.x : pd.y, acc[u]);
+        }
+    }
+    // accumulator: lane l, register i holds row (vector) 4*(l/16)+i for the
+    // f32 MFMA, 4*i+l/16 for the f64 MFMA; column = lane & 15 = (jj, re|im)
+    T *part = reinterpret_cast<T *>(a.part);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int j = 8 * tile[u] + jj;
+        if (j >= a.nbeta) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = sizeof(T) == 8 ? 4 * i + k : 4 * k + i;
+            const int64_t c = vb16 + v;
+            if (c < a.nvec) part[(((size_t)pair[u] * a.nbeta + j) * a.nvec + c) * 2 + odd] = acc[u][i];
+        }
+    }
+}
 
-    const int64_t nvb = (a.nvec + VBP - 1) / VBP;
+template <typename T>
+__global__ __launch_bounds__(kThreads) void proj_kernel(ProjParams a) {
+    __shared__ int gtab[kProjMaxNodes];
+    __shared__ T sc[kProjMaxNodes];
+    const int64_t nvb = (a.nvec + 63) / 64;  // 64 vectors per workgroup, 16 per wave
     const int64_t t_log = xcd_remap(blockIdx.x, a.ncl * nvb);
     const int64_t ci = t_log / nvb, vb = t_log - ci * nvb;
     const int64_t e = a.cells[ci];
     const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int I = tid; I < NP; I += kThreads) {
-        int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
-        ijk[I] = i | (j << 8) | (k << 16);
+    const T *dinv = (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr;
+    for (int I = threadIdx.x; I < a.n; I += kThreads) {
+        const int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
+        const int64_t g = gnode_of(i | (j << 8) | (k << 16), ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+        gtab[I] = (int)g;
+        sc[I] = dinv ? dinv[g] : T(1);
     }
     __syncthreads();
-    {
-        const TC *X = reinterpret_cast<const TC *>(a.X);
-        const T *dinv = (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr;
-        constexpr int TOT = NP * 2 * VBP, ITER = (TOT + kThreads - 1) / kThreads;
-        TC z[ITER];
-        T sc[ITER];
-#pragma unroll
-        for (int u = 0; u < ITER; ++u) {
-            const int idx = tid + u * kThreads;
-            const int v = idx % VBP, s = (idx / VBP) & 1, I = idx / (2 * VBP);
-            const int64_t col = vb * VBP + v;
-            z[u] = TC{0, 0};
-            sc[u] = T(1);
-            if (idx < TOT && I < a.n && col < a.nvec) {
-                const int64_t g = gnode_of(ijk[I], ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
-                z[u] = X[(2 * g + s) * a.ld + col];
-                if (dinv) sc[u] = dinv[g];
-            }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t vb16 = vb * 64 + wave * 16;
+    if (vb16 >= a.nvec) return;
+    const int pb = a.cell_pair_ptr[e];
+    const int nunits = (a.cell_pair_ptr[e + 1] - pb) * a.ntile;
+    for (int u0 = 0; u0 < nunits; u0 += kProjMaxUnits) {
+        switch (min(kProjMaxUnits, nunits - u0)) {
+            case 1: proj_pass<T, 1>(a, gtab, sc, vb16, u0, pb, lane); break;
+            case 2: proj_pass<T, 2>(a, gtab, sc, vb16, u0, pb, lane); break;
+            case 3: proj_pass<T, 3>(a, gtab, sc, vb16, u0, pb, lane); break;
+            default: proj_pass<T, 4>(a, gtab, sc, vb16, u0, pb, lane); break;
         }
-#pragma unroll
-        for (int u = 0; u < ITER; ++u) {
-            const int idx = tid + u * kThreads;
-            const int v = idx % VBP, s = (idx / VBP) & 1, I = idx / (2 * VBP);
-            if (idx < TOT) {
-                xs[(4 * I + 2 * s) * VBP + v] = z[u].x * sc[u];
-                xs[(4 * I + 2 * s + 1) * VBP + v] = z[u].y * sc[u];
-            }
-        }
-    }
-    __syncthreads();
-    const int kr = lane >> 4, cn = lane & 15;
-    const int sB = kr >> 1, rB = kr & 1;
-    const int nchunk = (a.n + 3) / 4;
-    const int I0 = wave * nchunk, I1 = min(a.n, I0 + nchunk);
-    const int ntile = (2 * a.nbeta + 15) / 16;
-    const int pb = a.cell_pair_ptr[e], pe = a.cell_pair_ptr[e + 1];
-    for (int pp = pb; pp < pe; ++pp) {
-        const int pair = a.cell_pairs[pp];
-        const TC *P = reinterpret_cast<const TC *>(a.P) + (size_t)pair * NP * 2 * a.nbeta;
-        for (int nt = 0; nt < ntile; ++nt) {
-            const int ncol = nt * 16 + cn, j = ncol >> 1, out = ncol & 1;
-            const bool jv = j < a.nbeta;
-            acc_t acc = acc_t{0, 0, 0, 0};
-            // P values of the next PF nodes stay in flight (register ring)
-            constexpr int PF = 16;
-            const TC *pcol = P + sB * a.nbeta + j;
-            TC pbuf[PF];
-#pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                const int I = I0 + u;
-                pbuf[u] = (jv && I < I1) ? pcol[(size_t)I * 2 * a.nbeta] : TC{0, 0};
-            }
-            for (int Ib = I0; Ib < I1; Ib += PF) {
-#pragma unroll
-                for (int u = 0; u < PF; ++u) {
-                    const int I = Ib + u;
-                    const TC pv = pbuf[u];
-                    const int In = I + PF;
-                    pbuf[u] = (jv && In < I1) ? pcol[(size_t)In * 2 * a.nbeta] : TC{0, 0};
-                    if (I < I1) {
-                        T av = cn < VBP ? xs[(4 * I + kr) * VBP + cn] : T(0);
-                        T bv = rB == 0 ? (out == 0 ? pv.x : -pv.y) : (out == 0 ? pv.y : pv.x);
-                        acc = MM<T>::mma(av, bv, acc);
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) red[wave][nt][lane * 4 + i] = acc[i];
-        }
-        __syncthreads();
-        // sum the four node chunks in a fixed order and store
-        for (int o = tid; o < ntile * 256; o += kThreads) {
-            const int nt = o >> 8, li = (o & 255) >> 2, i = o & 3;
-            T s = red[0][nt][o & 255] + red[1][nt][o & 255] + red[2][nt][o & 255] + red[3][nt][o & 255];
-            const int ccol = li & 15, kl = li >> 4;
-            const int v = sizeof(T) == 8 ? 4 * i + kl : 4 * kl + i;  // accumulator row
-            const int ncol = nt * 16 + ccol, j = ncol >> 1, out = ncol & 1;
-            const int64_t col = vb * VBP + v;
-            if (v < VBP && j < a.nbeta && col < a.nvec)
-                reinterpret_cast<T *>(a.part)[(((size_t)pair * a.nbeta + j) * a.nvec + col) * 2 + out] = s;
-        }
-        __syncthreads();
     }
 }
 
@@ -541,15 +622,20 @@ __global__ void setup_fields_kernel(const double *V, const double *B, const doub
 // P[pair][I][s][j] = sum_q wq[q] Phi[q][I] phi[pair][q][s][j]
 __global__ void setup_proj_kernel(const cd *phi, const double *Phi, const double *wq, cd *P64,
                                   cf *P32, int64_t npairs, int n, int nq, int NP, int nbeta) {
+    // P[pair][tile][I][j % 8][spin] = sum_q w_q Phi_I(q) phi[pair][q][spin][j], zero when
+    // I >= n or j >= nbeta
+    const int ntile = (nbeta + 7) / 8;
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t per = (int64_t)NP * 2 * nbeta;
+    const int64_t per = (int64_t)ntile * NP * 16;
     if (idx >= npairs * per) return;
-    int64_t pair = idx / per;
+    const int64_t pair = idx / per;
     int r = (int)(idx % per);
-    int I = r / (2 * nbeta), sj = r % (2 * nbeta);
+    const int tile = r / (NP * 16);
+    r -= tile * NP * 16;
+    const int I = r >> 4, j = 8 * tile + ((r >> 1) & 7), sp = r & 1;
     double ar = 0, ai = 0;
-    if (I < n) {
-        const cd *ph = phi + (size_t)pair * nq * 2 * nbeta + sj;
+    if (I < n && j < nbeta) {
+        const cd *ph = phi + (size_t)pair * nq * 2 * nbeta + sp * nbeta + j;
         for (int q = 0; q < nq; ++q) {
             double w = wq[q] * Phi[(size_t)q * NP + I];
             cd z = ph[(size_t)q * 2 * nbeta];
@@ -604,11 +690,15 @@ __global__ void dinv_kernel(const double *D, double *d64, float *d32, int64_t M)
 // ---------------------------------------------------------------------------
 template <typename T, int MT, int NP>
 static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha, const void *X,
-                           void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+                           void *Y, int64_t nvec, int64_t ld, hipStream_t s, const InitTerms *init) {
     const Mesh &m = c->m;
     const Layout &L = c->L;
     constexpr bool dbl = sizeof(T) == 8;
     CellParams a{};
+    if (flags & FLAG_INIT) {
+        if (!init || !init->Zk || !init->R || (flags & FLAG_ACCUM)) return hipErrorInvalidValue;
+        set_init(a, *init);
+    }
     a.X = X; a.Y = Y; a.ld = ld; a.nvec = nvec;
     a.ncx = m.ncell[0]; a.ncy = m.ncell[1];
     a.Nx = m.Nd[0]; a.Ny = m.Nd[1]; a.Nz = m.Nd[2];
@@ -648,28 +738,30 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
     return hipSuccess;
 }
 
-template <typename T, int VBP, int NP>
+template <typename T>
 static hipError_t run_proj(const chfsi_ctx *c, int flags, const void *X, int64_t nvec, int64_t ld,
                            hipStream_t s) {
     const Mesh &m = c->m;
     const Layout &L = c->L;
     constexpr bool dbl = sizeof(T) == 8;
+    if (m.n > kProjMaxNodes) return hipErrorInvalidValue;
     ProjParams a{};
     a.X = X; a.ld = ld; a.nvec = nvec;
     a.cells = c->P<int>(L.nl_cells);
     a.ncl = m.n_nl_cells;
     a.ncx = m.ncell[0]; a.ncy = m.ncell[1];
     a.Nx = m.Nd[0]; a.Ny = m.Nd[1]; a.Nz = m.Nd[2];
-    a.p = m.p; a.n1 = m.n1; a.n = m.n;
+    a.p = m.p; a.n1 = m.n1; a.n = m.n; a.npad = m.npad;
     a.dinv = dbl ? c->P<char>(L.Dinv64) : c->P<char>(L.Dinv32);
     a.cell_pair_ptr = c->P<int>(L.cell_pair_ptr);
     a.cell_pairs = c->P<int>(L.cell_pairs);
     a.P = dbl ? c->P<char>(L.P64) : c->P<char>(L.P32);
     a.part = c->S<char>(L.partial);
     a.nbeta = m.nbeta;
+    a.ntile = (m.nbeta + 7) / 8;
     a.flags = flags;
-    const int64_t nvb = (nvec + VBP - 1) / VBP;
-    hipLaunchKernelGGL((proj_kernel<T, VBP, NP>), dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
+    const int64_t nvb = (nvec + 63) / 64;
+    hipLaunchKernelGGL((proj_kernel<T>), dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int64_t nthr = m.natoms * nvec;
@@ -715,22 +807,22 @@ static hipError_t run_adjoint(const chfsi_ctx *c, const void *X, const void *G, 
     }
 
 hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
-                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s,
+                          const InitTerms *init) {
     if (prec == CHFSI_FP64) {
-        CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
+        CHFSI_DISPATCH_NP(c->m.npad,
+                          return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s, init)));
     }
-    if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s);
-    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 4, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
+    if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s, init);
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 4, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s, init)));
 }
 
 // the projection of the bfloat16 path runs in float (complex64 blocks)
 hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags, const void *X,
                                   int64_t nvec, int64_t ld, hipStream_t s) {
     if (c->m.npairs == 0 || c->m.n_nl_cells == 0) return hipSuccess;
-    if (prec == CHFSI_FP64) {
-        CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<double, 8, NP>(c, flags, X, nvec, ld, s)));
-    }
-    CHFSI_DISPATCH_NP(c->m.npad, return (run_proj<float, 16, NP>(c, flags, X, nvec, ld, s)));
+    if (prec == CHFSI_FP64) return run_proj<double>(c, flags, X, nvec, ld, s);
+    return run_proj<float>(c, flags, X, nvec, ld, s);
 }
 
 hipError_t launch_adjoint_fields(const chfsi_ctx *c, chfsi_prec prec, const void *X, const void *G,
@@ -752,7 +844,7 @@ hipError_t launch_setup_fields(const chfsi_ctx *c, const double *V, const double
 hipError_t launch_setup_projectors(const chfsi_ctx *c, const cd *phi_dev, hipStream_t s) {
     const Mesh &m = c->m;
     if (m.npairs == 0) return hipSuccess;
-    const int64_t nthr = m.npairs * m.npad * 2 * m.nbeta;
+    const int64_t nthr = m.npairs * ((m.nbeta + 7) / 8) * m.npad * 16;
     hipLaunchKernelGGL(setup_proj_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, phi_dev,
                        c->P<double>(c->L.Phi64), c->P<double>(c->L.Wq), c->P<cd>(c->L.P64),
                        c->P<cf>(c->L.P32), m.npairs, m.n, m.nq, m.npad, m.nbeta);
