@@ -115,8 +115,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=60)
     ap.add_argument("--hx-only", action="store_true",
-                    help="only the H X products (for counter runs) and a 1 GiB device copy that calibrates "
-                         "the memory counters")
+                    help="only the H X products (for counter runs), after a 1 GiB fill and a 1 GiB sum that "
+                         "calibrate the memory counters")
     ap.add_argument("--hx-precs", default="fp64,fp32,bf16")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -145,13 +145,12 @@ def main():
         return
 
     if args.hx_only:
-        # a plain copy of 1 GiB: reads and writes 2^30 bytes each
+        # memory-counter calibration: a fill writes 2^30 bytes, a sum reads them
         a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
         a.fill_(1.0)
-        b.copy_(a)
+        a.sum().item()
         torch.cuda.synchronize()
-        del a, b
+        del a
 
     # ---- isolated H X per precision (nhx vectors)
     hx = {}

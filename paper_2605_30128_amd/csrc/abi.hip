@@ -519,11 +519,12 @@ int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds,
     for (int k = 1; k < degree; ++k) {
         const double sn = 1.0 / (2.0 / s1 - sk);
         const double a = 2.0 * sn / e;
-        // Z_{k+1} = a H D^{-1} Z_k - a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k: the
-        // recurrence terms are added by the cell kernel where it first writes a node
+        // Z_{k+1} = -a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k
+        HIPCHK(c, launch_filter_init_ld(rows, nvec, nvec, ld, z32, Zn, Zc, k > 1 ? Zp : nullptr, R, -a * cc,
+                                        -sk * sn, lamk + (int64_t)k * nvec, a, s));
+        // Z_{k+1} += a H D^{-1} Z_k
         if (nl) HIPCHK(c, launch_nonlocal_coeffs(c, prec, FLAG_DINV, Zc, nvec, nvec, s));
-        const InitTerms it{Zc, k > 1 ? Zp : nullptr, R, ld, -a * cc, -sk * sn, a, lamk + (int64_t)k * nvec};
-        HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_INIT | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s, &it));
+        HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_ACCUM | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s));
         void *t = Zp; Zp = Zc; Zc = Zn; Zn = t;
         sk = sn;
     }

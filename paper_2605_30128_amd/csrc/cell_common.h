@@ -31,40 +31,7 @@ struct CellParams {
     int ldw;      // row length of the bfloat16 w|J| phi table
     int64_t ldd;  // row length of the projector coefficients d
     int mode, flags;
-    // FLAG_INIT: the first touch of a node stores alpha (.) plus the
-    // recurrence terms beta Zk + gamma Zkm + rscale lam[col] R, formed in
-    // double and rounded once (Zk, Zkm: same layout as Y; R: complex128
-    // rows of length ldr; Zkm and lam may be null)
-    const void *Zk, *Zkm, *R;
-    int64_t ldr;
-    double beta, gamma, rscale;
-    const double *lam;
 };
-
-inline void set_init(CellParams &a, const InitTerms &t) {
-    a.Zk = t.Zk; a.Zkm = t.Zkm; a.R = t.R; a.ldr = t.ldr;
-    a.beta = t.beta; a.gamma = t.gamma; a.rscale = t.rscale; a.lam = t.lam;
-}
-
-// recurrence terms of row `row` (= 2 g + spin), column col, at Y-layout offset zoff
-template <typename TC>
-__device__ __forceinline__ TC init_terms(const CellParams &a, int64_t row, int64_t zoff, int64_t col) {
-    const double d = a.rscale * (a.lam ? a.lam[col] : 1.0);
-    const cd r = reinterpret_cast<const cd *>(a.R)[row * a.ldr + col];
-    double vx = d * r.x, vy = d * r.y;
-    const TC zk = reinterpret_cast<const TC *>(a.Zk)[zoff];
-    vx += a.beta * (double)zk.x;
-    vy += a.beta * (double)zk.y;
-    if (a.Zkm) {
-        const TC zm = reinterpret_cast<const TC *>(a.Zkm)[zoff];
-        vx += a.gamma * (double)zm.x;
-        vy += a.gamma * (double)zm.y;
-    }
-    TC o;
-    o.x = (decltype(o.x))vx;
-    o.y = (decltype(o.y))vy;
-    return o;
-}
 
 // global node of the local node packed as i | j << 8 | k << 16 in cell (ex, ey, ez)
 __device__ __forceinline__ int64_t gnode_of(int ijk, int64_t ex, int64_t ey, int64_t ez, int p,

@@ -61,39 +61,55 @@ template <typename T> __device__ __forceinline__ void rinv(int r, int &v, int &c
     if (sizeof(T) == 8) { v = r & 3; comp = r >> 2; } else { v = r >> 2; comp = r & 3; }
 }
 
-// Gathers the vector block of one cell into LDS as xs[I][rcol(v, 2s + r)].
-template <typename T, int VB, int NP, int XS>
-__device__ __forceinline__ void gather_block(T *xs, const int *ijk, const void *Xv, int64_t ld,
-                                             int64_t nvec, int64_t col0, int n, int64_t ex,
-                                             int64_t ey, int64_t ez, int p, int64_t Nx,
-                                             int64_t Ny, int64_t Nz, const T *dinv) {
+// Gathers the vector block of one cell into LDS as xs[I][rcol(v, 2s + r)]
+// (scaled by gsc[I] when gsc is given); grow[I] = 2 g(I) is the node's first
+// spinor row.
+template <typename T, int VB, int NP, int XS, int TH = kThreads>
+__device__ __forceinline__ void gather_block(T *xs, const int *grow, const T *gsc, const void *Xv, int64_t ld,
+                                             int64_t nvec, int64_t col0, int n) {
     using TC = typename Cplx<T>::type;
     const TC *X = reinterpret_cast<const TC *>(Xv);
-    constexpr int TOT = NP * 2 * VB, ITER = (TOT + kThreads - 1) / kThreads;
+    constexpr int TOT = NP * 2 * VB, ITER = (TOT + TH - 1) / TH;
     // all loads of this thread are issued before the first LDS store
     TC z[ITER];
     T sc[ITER];
 #pragma unroll
     for (int u = 0; u < ITER; ++u) {
-        const int idx = threadIdx.x + u * kThreads;
+        const int idx = threadIdx.x + u * TH;
         const int v = idx % VB, s = (idx / VB) & 1, I = idx / (2 * VB);
         const int64_t col = col0 + v;
         z[u] = TC{0, 0};
         sc[u] = T(1);
         if (idx < TOT && I < n && col < nvec) {
-            const int64_t g = gnode_of(ijk[I], ex, ey, ez, p, Nx, Ny, Nz);
-            z[u] = X[(2 * g + s) * ld + col];
-            if (dinv) sc[u] = dinv[g];
+            z[u] = X[(int64_t)(grow[I] + s) * ld + col];
+            if (gsc) sc[u] = gsc[I];
         }
     }
 #pragma unroll
     for (int u = 0; u < ITER; ++u) {
-        const int idx = threadIdx.x + u * kThreads;
+        const int idx = threadIdx.x + u * TH;
         const int v = idx % VB, s = (idx / VB) & 1, I = idx / (2 * VB);
         if (idx < TOT) {
             xs[I * XS + rcol<T>(v, 2 * s)] = z[u].x * sc[u];
             xs[I * XS + rcol<T>(v, 2 * s + 1)] = z[u].y * sc[u];
         }
+    }
+}
+
+// node tables of cell (ex, ey, ez): packed local indices, first spinor rows
+// and (when dinv is given) D^-1 values
+template <typename T>
+__device__ __forceinline__ void cell_tables(int *ijk, int *grow, T *gsc, const T *dinv, int NP, int n, int n1,
+                                            int64_t ex, int64_t ey, int64_t ez, int p, int64_t Nx, int64_t Ny,
+                                            int64_t Nz) {
+    for (int I = threadIdx.x; I < NP; I += blockDim.x) {
+        const int i = I % n1, j = (I / n1) % n1, k = I / (n1 * n1);
+        const int c = i | (j << 8) | (k << 16);
+        ijk[I] = c;
+        int64_t g = 0;
+        if (I < n) g = gnode_of(c, ex, ey, ez, p, Nx, Ny, Nz);
+        grow[I] = (int)(2 * g);
+        if (gsc) gsc[I] = (dinv && I < n) ? dinv[g] : T(1);
     }
 }
 
@@ -115,104 +131,44 @@ __device__ __forceinline__ void mfma_panel(typename MM<T>::acc *acc, const T *as
         }
         return;
     }
-    T bc[NTW];
+    // the B fragments of the next PD k-steps are in flight in a register
+    // ring; each step's reload is issued after its MFMAs (one step ahead
+    // measured fastest: deeper rings and issuing before the MFMAs were slower)
+    constexpr int PD = 1, NK = NP / 4;
+    static_assert(NK % PD == 0, "k steps per prefetch ring");
+    T bq[PD][NTW];
 #pragma unroll
-    for (int t = 0; t < NTW; ++t) bc[t] = bp[16 * t];
-    for (int kk = 0; kk < NP; kk += 4) {
-        const int kn = kk + 4 < NP ? kk + 4 : kk;
-        T bn[NTW];
+    for (int u = 0; u < PD; ++u)
 #pragma unroll
-        for (int t = 0; t < NTW; ++t) bn[t] = bp[(size_t)kn * NP + 16 * t];
-        T av = ap[kk * XS];
+        for (int t = 0; t < NTW; ++t) bq[u][t] = bp[(size_t)(4 * u) * NP + 16 * t];
+    for (int k0 = 0; k0 < NK; k0 += PD) {
 #pragma unroll
-        for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, bc[t], acc[t]);
-#pragma unroll
-        for (int t = 0; t < NTW; ++t) bc[t] = bn[t];
-    }
-}
-
-// The shared table of a panel staged through LDS in slices of KS rows of
-// its [k][NP] layout (a slice is contiguous in memory, so it is fetched with
-// 16-byte loads by all 256 threads), double buffered: the next slice is in
-// flight in registers while the MFMAs of the current one run.  Each table
-// byte then crosses L2 once per workgroup instead of once per wave.  Rows
-// are padded so that the four k rows a wave reads per MFMA fall on disjoint
-// LDS banks.
-template <typename T, int NP> struct Stage {
-    static constexpr int KS = sizeof(T) == 8 ? 8 : 16;
-    static constexpr int PAD = sizeof(T) == 8 ? 16 : (16 - NP % 64 + 64) % 64;
-    static constexpr int BS = NP + PAD;
-    static constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
-    static constexpr int CH = KS * NP / EPC;
-    static constexpr int IT = (CH + kThreads - 1) / kThreads;
-    static constexpr int NS = NP / KS;
-    static constexpr size_t bytes = 2 * (size_t)KS * BS * sizeof(T);
-};
-typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-
-template <typename T, int NP>
-__device__ __forceinline__ void stage_load(u4 *r, const T *B, int k0) {
-    using S = Stage<T, NP>;
-    const u4 *src = reinterpret_cast<const u4 *>(B + (size_t)k0 * NP);
-#pragma unroll
-    for (int u = 0; u < S::IT; ++u) {
-        const int c = threadIdx.x + u * kThreads;
-        if (c < S::CH) r[u] = src[c];
-    }
-}
-template <typename T, int NP>
-__device__ __forceinline__ void stage_store(const u4 *r, T *bs) {
-    using S = Stage<T, NP>;
-#pragma unroll
-    for (int u = 0; u < S::IT; ++u) {
-        const int c = threadIdx.x + u * kThreads;
-        if (c < S::CH) {
-            const int e = c * S::EPC, row = e / NP, col = e - row * NP;
-            *reinterpret_cast<u4 *>(bs + row * S::BS + col) = r[u];
-        }
-    }
-}
-
-// as mfma_panel, with B read from LDS slices; all threads of the workgroup
-// must call it (it contains barriers) and it ends with a barrier
-template <typename T, int NTW, int NP, int XS>
-__device__ __forceinline__ void mfma_panel_staged(typename MM<T>::acc *acc, const T *as, const T *B, T *bs,
-                                                  int m, int nt0, int lane) {
-    using S = Stage<T, NP>;
-    const int kr = lane >> 4, cn = lane & 15;
-    u4 r[S::IT];
-    stage_load<T, NP>(r, B, 0);
-    stage_store<T, NP>(r, bs);
-    __syncthreads();
-#pragma unroll 1
-    for (int s = 0; s < S::NS; ++s) {
-        const T *cur = bs + (s & 1) * S::KS * S::BS + kr * S::BS + nt0 * 16 + cn;
-        if (s + 1 < S::NS) stage_load<T, NP>(r, B, (s + 1) * S::KS);
-        const T *ap = as + (s * S::KS + kr) * XS + 16 * m + cn;
-#pragma unroll
-        for (int kk = 0; kk < S::KS; kk += 4) {
+        for (int u = 0; u < PD; ++u) {
+            const int kk = 4 * (k0 + u);
             const T av = ap[kk * XS];
 #pragma unroll
-            for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, cur[kk * S::BS + 16 * t], acc[t]);
+            for (int t = 0; t < NTW; ++t) acc[t] = MM<T>::mma(av, bq[u][t], acc[t]);
+            const int kn = k0 + u + PD < NK ? kk + 4 * PD : kk;
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) bq[u][t] = bp[(size_t)kn * NP + 16 * t];
         }
-        if (s + 1 < S::NS) stage_store<T, NP>(r, bs + ((s + 1) & 1) * S::KS * S::BS);
-        __syncthreads();
     }
 }
 
+// One workgroup per (cell, VB = 4 MT vectors): its waves split the 16 MT
+// rows x NP columns of the block MT (16-row tiles) x WN (column groups of
+// NTW 16-column tiles).
 template <typename T, int MT, int NP>
-__global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
+__global__ __launch_bounds__(kCellThreads) void cell_kernel(CellParams a) {
     using TC = typename Cplx<T>::type;
     using acc_t = typename MM<T>::acc;
     constexpr int CB = 16 * MT, VB = 4 * MT;
     constexpr int XS = CB + LdsPad<T>::v;
-    constexpr int NT = NP / 16, WN = 4 / MT, NTW = NT / WN;
-    static_assert(NT % WN == 0, "tile split");
-    // stage the tables through LDS where the block leaves room for two slices
-    constexpr bool STAGED = NP * XS * sizeof(T) + Stage<T, NP>::bytes + NP * sizeof(int) <= 158 * 1024;
+    constexpr int NT = NP / 16, WN = kCellThreads / 64 / MT, NTW = NT / WN;
+    static_assert(NT % WN == 0, "column tiles split evenly over the wave groups");
     __shared__ __attribute__((aligned(16))) T xs[NP * XS];
-    __shared__ __attribute__((aligned(16))) T bs[STAGED ? Stage<T, NP>::bytes / sizeof(T) : 1];
-    __shared__ int ijk[NP];
+    __shared__ int ijk[NP], grow[NP];
+    __shared__ T gsc[NP];
 
     const int64_t nvb = (a.nvec + VB - 1) / VB;
     const int64_t t_log = xcd_remap(blockIdx.x, a.ncl * nvb);
@@ -222,32 +178,23 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = wave % MT, nt0 = (wave / MT) * NTW;
 
-    for (int I = tid; I < NP; I += kThreads) {
-        int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
-        ijk[I] = i | (j << 8) | (k << 16);
-    }
+    const bool scaled = (a.flags & FLAG_DINV) != 0;
+    cell_tables<T>(ijk, grow, gsc, scaled ? reinterpret_cast<const T *>(a.dinv) : nullptr, NP, a.n, a.n1, ex, ey,
+                   ez, a.p, a.Nx, a.Ny, a.Nz);
     __syncthreads();
-    gather_block<T, VB, NP, XS>(xs, ijk, a.X, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
-                                a.Ny, a.Nz,
-                                (a.flags & FLAG_DINV) ? reinterpret_cast<const T *>(a.dinv) : nullptr);
+    gather_block<T, VB, NP, XS, kCellThreads>(xs, grow, scaled ? gsc : nullptr, a.X, a.ld, a.nvec, vb * VB, a.n);
     __syncthreads();
 
     acc_t y[NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) y[t] = acc_t{0, 0, 0, 0};
-    if constexpr (STAGED)
-        mfma_panel_staged<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bk), bs, m, nt0, lane);
-    else
-        mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bk), m, nt0, lane);
+    mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bk), m, nt0, lane);
 
     if (a.mode == MODE_HAM) {
         acc_t tq[NTW];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) tq[t] = acc_t{0, 0, 0, 0};
-        if constexpr (STAGED)
-            mfma_panel_staged<T, NTW, NP, XS>(tq, xs, reinterpret_cast<const T *>(a.BphiT), bs, m, nt0, lane);
-        else
-            mfma_panel<T, NTW, NP, XS>(tq, xs, reinterpret_cast<const T *>(a.BphiT), m, nt0, lane);
+        mfma_panel<T, NTW, NP, XS>(tq, xs, reinterpret_cast<const T *>(a.BphiT), m, nt0, lane);
         // pointwise (V + B.sigma) w|J| on (re up, im up, re down, im down)
         const T *W = reinterpret_cast<const T *>(a.W) + (size_t)e * NP * 4;
 #pragma unroll
@@ -296,10 +243,7 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
             for (int i = 0; i < 4; ++i) xs[q * XS + rcol<T>(vl, i)] = tq[t][i];
         }
         __syncthreads();
-        if constexpr (STAGED)
-            mfma_panel_staged<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), bs, m, nt0, lane);
-        else
-            mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
+        mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
     }
 
     // colour-ordered assembly: the previous values of all the lane's nodes
@@ -308,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
     const int64_t col = vb * VB + 4 * m + (lane >> 4);
     if (col < a.nvec) {
         const T al = (T)a.alpha;
-        const bool accum = (a.flags & FLAG_ACCUM) != 0, init = (a.flags & FLAG_INIT) != 0;
+        const bool accum = (a.flags & FLAG_ACCUM) != 0;
         int64_t off[NTW];
         TC o0[NTW], o1[NTW];
 #pragma unroll
@@ -319,14 +263,11 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellParams a) {
             o1[t] = TC{0, 0};
             if (J < a.n) {
                 const int c = ijk[J];
-                const int64_t row = 2 * gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+                const int64_t row = grow[J];
                 off[t] = row * a.ld + col;
                 if (!first_touch(c, a.p, a.px, a.py, a.pz, accum)) {
                     o0[t] = Y[off[t]];
                     o1[t] = Y[off[t] + a.ld];
-                } else if (init) {
-                    o0[t] = init_terms<TC>(a, row, off[t], col);
-                    o1[t] = init_terms<TC>(a, row + 1, off[t] + a.ld, col);
                 }
             }
         }
@@ -517,17 +458,14 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams a) {
     constexpr int XS = CB + LdsPad<T>::v;
     constexpr int NT = NP / 16, WN = 4 / MT, NTW = NT / WN;
     __shared__ __attribute__((aligned(16))) T xs[NP * XS];
-    __shared__ int ijk[NP];
+    __shared__ int ijk[NP], grow[NP];
     static_assert(NP * XS * sizeof(T) >= 4 * NP * sizeof(double), "reduction buffer");
 
     const int64_t e = blockIdx.x;
     const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = wave % MT, nt0 = (wave / MT) * NTW;
-    for (int I = tid; I < NP; I += kThreads) {
-        int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
-        ijk[I] = i | (j << 8) | (k << 16);
-    }
+    cell_tables<T>(ijk, grow, nullptr, nullptr, NP, a.n, a.n1, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
     double sv[NTW], sx[NTW], sy[NTW], sz[NTW];
 #pragma unroll
     for (int t = 0; t < NTW; ++t) { sv[t] = 0; sx[t] = 0; sy[t] = 0; sz[t] = 0; }
@@ -535,16 +473,14 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams a) {
     const int64_t nvb = (a.nvec + VB - 1) / VB;
     for (int64_t vb = 0; vb < nvb; ++vb) {
         __syncthreads();
-        gather_block<T, VB, NP, XS>(xs, ijk, a.X, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
-                                    a.Ny, a.Nz, nullptr);
+        gather_block<T, VB, NP, XS>(xs, grow, nullptr, a.X, a.ld, a.nvec, vb * VB, a.n);
         __syncthreads();
         acc_t tx[NTW], tg[NTW];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) { tx[t] = acc_t{0, 0, 0, 0}; tg[t] = acc_t{0, 0, 0, 0}; }
         mfma_panel<T, NTW, NP, XS, false>(tx, xs, BphiT, m, nt0, lane);
         __syncthreads();
-        gather_block<T, VB, NP, XS>(xs, ijk, a.G, a.ld, a.nvec, vb * VB, a.n, ex, ey, ez, a.p, a.Nx,
-                                    a.Ny, a.Nz, nullptr);
+        gather_block<T, VB, NP, XS>(xs, grow, nullptr, a.G, a.ld, a.nvec, vb * VB, a.n);
         __syncthreads();
         mfma_panel<T, NTW, NP, XS, false>(tg, xs, BphiT, m, nt0, lane);
 #pragma unroll
@@ -690,15 +626,11 @@ __global__ void dinv_kernel(const double *D, double *d64, float *d32, int64_t M)
 // ---------------------------------------------------------------------------
 template <typename T, int MT, int NP>
 static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha, const void *X,
-                           void *Y, int64_t nvec, int64_t ld, hipStream_t s, const InitTerms *init) {
+                           void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
     const Mesh &m = c->m;
     const Layout &L = c->L;
     constexpr bool dbl = sizeof(T) == 8;
     CellParams a{};
-    if (flags & FLAG_INIT) {
-        if (!init || !init->Zk || !init->R || (flags & FLAG_ACCUM)) return hipErrorInvalidValue;
-        set_init(a, *init);
-    }
     a.X = X; a.Y = Y; a.ld = ld; a.nvec = nvec;
     a.ncx = m.ncell[0]; a.ncy = m.ncell[1];
     a.Nx = m.Nd[0]; a.Ny = m.Nd[1]; a.Nz = m.Nd[2];
@@ -731,7 +663,7 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
         a.cells = c->P<int>(L.colour_cells) + c->colour_ptr[col];
         a.ncl = ncl;
         a.px = col & 1; a.py = (col >> 1) & 1; a.pz = (col >> 2) & 1;
-        hipLaunchKernelGGL((cell_kernel<T, MT, NP>), dim3((unsigned)(ncl * nvb)), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((cell_kernel<T, MT, NP>), dim3((unsigned)(ncl * nvb)), dim3(kCellThreads), 0, s, a);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -807,14 +739,12 @@ static hipError_t run_adjoint(const chfsi_ctx *c, const void *X, const void *G, 
     }
 
 hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
-                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s,
-                          const InitTerms *init) {
+                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
     if (prec == CHFSI_FP64) {
-        CHFSI_DISPATCH_NP(c->m.npad,
-                          return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s, init)));
+        CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
     }
-    if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s, init);
-    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 4, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s, init)));
+    if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s);
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 4, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
 }
 
 // the projection of the bfloat16 path runs in float (complex64 blocks)

@@ -12,7 +12,8 @@
 
 namespace chfsi {
 
-constexpr int kThreads = 256;       // threads per workgroup of the cell kernels
+constexpr int kThreads = 256;       // threads per workgroup of the projection and adjoint kernels
+constexpr int kCellThreads = 256;   // threads per workgroup of the FP64/FP32 cell-operator kernel
 constexpr int kMaxN = 512;          // nodes per cell (p <= 7)
 constexpr int kMaxBeta = 16;
 constexpr int kMaxDegree = 256;     // Chebyshev degree limit (Lambda_k table)
@@ -93,24 +94,13 @@ enum : int {
     FLAG_ACCUM = 1,     // Y += alpha * (.) at every node (else first touch writes)
     FLAG_DINV = 2,      // gather D^{-1} X
     FLAG_NLOC = 4,      // add the spin-orbit epilogue (needs dcoef)
-    FLAG_INIT = 8,      // first touch adds the recurrence terms (CellParams Zk, Zkm, R)
 };
 
-// recurrence terms added at the first touch of each node (FLAG_INIT):
-// beta Zk + gamma Zkm + rscale lam[col] R (Zkm, lam nullable)
-struct InitTerms {
-    const void *Zk, *Zkm;
-    const cd *R;
-    int64_t ldr;
-    double beta, gamma, rscale;
-    const double *lam;
-};
 // apply the cell operator for all 8 colours: Y (+)= alpha * Op(X)
 hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
-                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s,
-                          const InitTerms *init = nullptr);
+                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s);
 hipError_t launch_cell_op_bf16(const chfsi_ctx *c, int mode, int flags, double alpha, const void *X,
-                               void *Y, int64_t nvec, int64_t ld, hipStream_t s, const InitTerms *init);
+                               void *Y, int64_t nvec, int64_t ld, hipStream_t s);
 // nonlocal projection + per-atom reduction with Delta: dcoef = Delta * P^H X
 hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags, const void *X,
                                   int64_t nvec, int64_t ld, hipStream_t s);
