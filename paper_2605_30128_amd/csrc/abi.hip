@@ -335,6 +335,46 @@ int read_flag(chfsi_ctx *c, hipStream_t s, int *out) {
     return CHFSI_OK;
 }
 
+// Blocked Cholesky A = L L^H of a row-major N x N Hermitian matrix (lower L,
+// strict upper triangle zeroed).  The column-major view of the buffer is
+// conj(A) = U^H U with U = L^T upper triangular, so the panels are BLAS-3
+// calls on that view: per block column j, the diagonal block is factored by
+// one workgroup, then U_12 <- U_11^{-H} A_12 (trsm) and A_22 -= U_12^H U_12
+// (herk).  flag = 1 if a pivot is below 64 eps (rank deficiency).
+int cholesky_blocked(chfsi_ctx *c, int N, cd *A, int *flag, hipStream_t s) {
+    constexpr int NB = 64;
+    BLASCHK(c, rocblas_set_stream(c->blas, s));
+    const rocblas_double_complex one{1.0, 0.0}, mone{-1.0, 0.0};
+    const double dmone = -1.0, done = 1.0;
+    auto rb = [](cd *p) { return reinterpret_cast<rocblas_double_complex *>(p); };
+    for (int j = 0; j < N; j += NB) {
+        const int nb = std::min(NB, N - j), m = N - j - nb;
+        cd *Ajj = A + (int64_t)j * N + j;
+        HIPCHK(c, launch_cholesky_block(nb, N, Ajj, flag, s));
+        if (m == 0) break;
+        cd *A12 = A + (int64_t)(j + nb) * N + j;  // column-major (j, j + nb)
+        BLASCHK(c, rocblas_ztrsm(c->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                                 rocblas_diagonal_non_unit, nb, m, &one, rb(Ajj), N, rb(A12), N));
+        BLASCHK(c, rocblas_zherk(c->blas, rocblas_fill_upper, rocblas_operation_conjugate_transpose, m, nb, &dmone,
+                                 rb(A12), N, &done, rb(A + (int64_t)(j + nb) * N + j + nb), N));
+    }
+    (void)mone;
+    HIPCHK(c, launch_zero_upper(N, A, s));
+    return CHFSI_OK;
+}
+
+// T = diag(scale) L^{-H} for the factor of cholesky_blocked: in the
+// column-major view T^T = U^{-H} diag(scale), one triangular solve.
+int tri_inv_scaled(chfsi_ctx *c, int N, cd *L, const double *scale, cd *T, hipStream_t s) {
+    BLASCHK(c, rocblas_set_stream(c->blas, s));
+    const rocblas_double_complex one{1.0, 0.0};
+    HIPCHK(c, launch_diag(N, scale, T, s));
+    BLASCHK(c, rocblas_ztrsm(c->blas, rocblas_side_left, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                             rocblas_diagonal_non_unit, N, N, &one, reinterpret_cast<rocblas_double_complex *>(L), N,
+                             reinterpret_cast<rocblas_double_complex *>(T), N));
+    return CHFSI_OK;
+}
+
 // S = A^H B (N x N row-major) for [rows][ld] blocks: column-major view of a
 // row-major block is its transpose, so S^T = Bcm * Acm^H in BLAS terms.
 // The reduction dimension (2M rows) is split into nb chunks computed as one
@@ -424,12 +464,12 @@ int orthonormalize_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64
         int rc = gram(c, Y, MY, nvec, ld, Sm, s);
         if (rc) return rc;
         HIPCHK(c, launch_herm_equilibrate((int)nvec, Sm, scale, flag, s));
-        HIPCHK(c, launch_cholesky((int)nvec, Sm, flag, s));
-        HIPCHK(c, launch_tri_inv_scale((int)nvec, Sm, scale, T, s));
+        if ((rc = cholesky_blocked(c, (int)nvec, Sm, flag, s))) return rc;
         int f = 0;
         rc = read_flag(c, s, &f);
         if (rc) return rc;
         if (f) return fail(c, CHFSI_E_NOT_SPD, "Cholesky-QR breakdown: the block is (numerically) rank deficient");
+        if ((rc = tri_inv_scaled(c, (int)nvec, Sm, scale, T, s))) return rc;
         if ((rc = rotate(c, Y, T, nvec, ld, s))) return rc;
         if (HY && (rc = rotate(c, HY, T, nvec, ld, s))) return rc;
         if ((rc = rotate(c, MY, T, nvec, ld, s))) return rc;
@@ -476,11 +516,11 @@ int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t l
     if ((rc = gram(c, Y, MY, nvec, ld, Sm, s))) return rc;
     if ((rc = gram(c, Y, HY, nvec, ld, Hs, s))) return rc;
     HIPCHK(c, launch_herm_equilibrate((int)nvec, Sm, scale, flag, s));
-    HIPCHK(c, launch_cholesky((int)nvec, Sm, flag, s));
-    HIPCHK(c, launch_tri_inv_scale((int)nvec, Sm, scale, T, s));
+    if ((rc = cholesky_blocked(c, (int)nvec, Sm, flag, s))) return rc;
     int f = 0;
     if ((rc = read_flag(c, s, &f))) return rc;
     if (f) return fail(c, CHFSI_E_NOT_SPD, "Cholesky of Y^H M Y broke down: the block is (numerically) rank deficient");
+    if ((rc = tri_inv_scaled(c, (int)nvec, Sm, scale, T, s))) return rc;
     if ((rc = small_mm(c, Hs, T, W, nvec, false, s))) return rc;   // W = Hs T
     if ((rc = small_mm(c, T, W, Cm, nvec, true, s))) return rc;    // C = T^H W
     HIPCHK(c, launch_hermitize((int)nvec, Cm, s));

@@ -76,47 +76,50 @@ hipError_t launch_hermitize(int N, cd *S, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// in-place Cholesky A = L L^H (lower; the strict upper triangle is zeroed).
-// One workgroup: right-looking, column by column.  The matrices factored
-// here are equilibrated to a unit diagonal, so a pivot below 64 eps means
-// the block is numerically rank deficient: flag = 1.
+// in-place Cholesky A = L L^H of an n x n diagonal block (row stride lda;
+// lower L, the block's strict upper triangle is zeroed).  One workgroup:
+// right-looking, column by column.  The matrices factored here are
+// equilibrated to a unit diagonal, so a pivot below 64 eps means the block
+// is numerically rank deficient: flag = 1.  The blocked factorization of the
+// whole matrix (panel solves and trailing updates as BLAS-3 calls) is
+// driven from the host.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void cholesky_kernel(int N, cd *A, int *flag) {
+__global__ __launch_bounds__(1024) void cholesky_block_kernel(int n, int lda, cd *A, int *flag) {
     __shared__ double djj;
     __shared__ int bad;
     const int tid = threadIdx.x, nt = blockDim.x;
     if (tid == 0) bad = 0;
     __syncthreads();
-    for (int j = 0; j < N; ++j) {
+    for (int j = 0; j < n; ++j) {
         if (tid == 0) {
-            double d = A[(int64_t)j * N + j].x;
+            double d = A[(int64_t)j * lda + j].x;
             if (!(d > 64.0 * 2.220446049250313e-16) || !isfinite(d)) {
                 bad = 1;
                 d = 1.0;
             }
             djj = sqrt(d);
-            A[(int64_t)j * N + j] = cd{djj, 0.0};
+            A[(int64_t)j * lda + j] = cd{djj, 0.0};
         }
         __syncthreads();
         if (bad) break;
         const double inv = 1.0 / djj;
-        for (int i = j + 1 + tid; i < N; i += nt) {
-            cd v = A[(int64_t)i * N + j];
+        for (int i = j + 1 + tid; i < n; i += nt) {
+            cd v = A[(int64_t)i * lda + j];
             v.x *= inv;
             v.y *= inv;
-            A[(int64_t)i * N + j] = v;
+            A[(int64_t)i * lda + j] = v;
         }
         __syncthreads();
-        const int m = N - j - 1;
-        for (int64_t idx = tid; idx < (int64_t)m * m; idx += nt) {
-            int i = j + 1 + (int)(idx / m), k = j + 1 + (int)(idx % m);
+        const int m = n - j - 1;
+        for (int idx = tid; idx < m * m; idx += nt) {
+            const int i = j + 1 + idx / m, k = j + 1 + idx % m;
             if (k > i) continue;
-            cd lij = A[(int64_t)i * N + j], lkj = A[(int64_t)k * N + j];
-            cd a = A[(int64_t)i * N + k];
-            // a -= lij * conj(lkj)
-            a.x -= lij.x * lkj.x + lij.y * lkj.y;
-            a.y -= lij.y * lkj.x - lij.x * lkj.y;
-            A[(int64_t)i * N + k] = a;
+            const cd lij = A[(int64_t)i * lda + j], lkj = A[(int64_t)k * lda + j];
+            cd v = A[(int64_t)i * lda + k];
+            // v -= lij * conj(lkj)
+            v.x -= lij.x * lkj.x + lij.y * lkj.y;
+            v.y -= lij.y * lkj.x - lij.x * lkj.y;
+            A[(int64_t)i * lda + k] = v;
         }
         __syncthreads();
     }
@@ -124,54 +127,44 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(int N, cd *A, int *flag)
         if (tid == 0) *flag = 1;
         return;
     }
-    for (int64_t idx = tid; idx < (int64_t)N * N; idx += nt) {
-        int i = (int)(idx / N), k = (int)(idx % N);
-        if (k > i) A[idx] = cd{0.0, 0.0};
+    for (int idx = tid; idx < n * n; idx += nt) {
+        const int i = idx / n, k = idx % n;
+        if (k > i) A[(int64_t)i * lda + k] = cd{0.0, 0.0};
     }
 }
 
-hipError_t launch_cholesky(int N, cd *A, int *flag, hipStream_t s) {
-    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, s, N, A, flag);
+hipError_t launch_cholesky_block(int n, int lda, cd *A, int *flag, hipStream_t s) {
+    hipLaunchKernelGGL(cholesky_block_kernel, dim3(1), dim3(1024), 0, s, n, lda, A, flag);
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// T = diag(scale) L^{-H}: solve L^H T = I (upper triangular T), one column
-// per thread, all threads walking the rows in lock step (broadcast reads of L).
-// ---------------------------------------------------------------------------
-__global__ void tri_inv_kernel(int N, const cd *L, const double *scale, cd *T) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool act = c < N;
-    for (int i = N - 1; i >= 0; --i) {
-        if (!act) continue;
-        cd s;
-        if (i > c) {
-            T[(int64_t)i * N + c] = cd{0.0, 0.0};
-            continue;
-        }
-        s.x = (i == c) ? 1.0 : 0.0;
-        s.y = 0.0;
-        for (int m = i + 1; m <= c; ++m) {
-            cd l = L[(int64_t)m * N + i];  // (L^H)[i][m] = conj(L[m][i])
-            cd t = T[(int64_t)m * N + c];
-            s.x -= l.x * t.x + l.y * t.y;
-            s.y -= l.x * t.y - l.y * t.x;
-        }
-        double d = L[(int64_t)i * N + i].x;
-        T[(int64_t)i * N + c] = cd{s.x / d, s.y / d};
-    }
-    if (!act) return;
-    if (scale)
-        for (int i = 0; i <= c; ++i) {
-            cd t = T[(int64_t)i * N + c];
-            t.x *= scale[i];
-            t.y *= scale[i];
-            T[(int64_t)i * N + c] = t;
-        }
+// zero the strict upper triangle of a row-major N x N matrix (the blocks
+// right of the diagonal blocks, which the blocked factorization leaves alone)
+__global__ void zero_upper_kernel(int N, cd *A) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const int i = (int)(idx / N), k = (int)(idx % N);
+    if (k > i) A[idx] = cd{0.0, 0.0};
 }
 
-hipError_t launch_tri_inv_scale(int N, const cd *L, const double *scale, cd *T, hipStream_t s) {
-    hipLaunchKernelGGL(tri_inv_kernel, dim3((N + 63) / 64), dim3(64), 0, s, N, L, scale, T);
+// T = diag(scale) (identity if scale is null), the right-hand side of the
+// triangular solve that forms diag(scale) L^{-H}
+__global__ void diag_kernel(int N, const double *scale, cd *T) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const int i = (int)(idx / N), k = (int)(idx % N);
+    T[idx] = cd{i == k ? (scale ? scale[i] : 1.0) : 0.0, 0.0};
+}
+
+hipError_t launch_zero_upper(int N, cd *A, hipStream_t s) {
+    const int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int N, const double *scale, cd *T, hipStream_t s) {
+    const int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(diag_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, scale, T);
     return hipGetLastError();
 }
 

@@ -137,8 +137,9 @@ hipError_t launch_axpby(int64_t n, double a, const cd *x, double b, cd *y, hipSt
 hipError_t launch_sum_parts(int64_t n, int nparts, const cd *parts, cd *out, hipStream_t s);
 hipError_t launch_herm_equilibrate(int N, cd *S, double *scale, int *flag, hipStream_t s);
 hipError_t launch_hermitize(int N, cd *S, hipStream_t s);
-hipError_t launch_cholesky(int N, cd *A, int *flag, hipStream_t s);
-hipError_t launch_tri_inv_scale(int N, const cd *L, const double *scale, cd *T, hipStream_t s);
+hipError_t launch_cholesky_block(int n, int lda, cd *A, int *flag, hipStream_t s);
+hipError_t launch_zero_upper(int N, cd *A, hipStream_t s);
+hipError_t launch_diag(int N, const double *scale, cd *T, hipStream_t s);
 hipError_t launch_jacobi_eig(int N, cd *A, cd *A2, cd *V, cd *V2, double *w, double *red,
                              int max_sweeps, hipStream_t s, int *sweeps_out, cd **Vout);
 

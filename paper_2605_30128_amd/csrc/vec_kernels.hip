@@ -35,6 +35,61 @@ __global__ void filter_init_kernel(int64_t rows, int64_t nvec, int64_t ldz, int6
     }
 }
 
+// Two adjacent complex values as doubles (16-byte aligned pairs of cf, or
+// two cd), and their store after rounding to TZ.
+__device__ __forceinline__ void load2(const cf *p, double v[4]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 z = *reinterpret_cast<const f4 *>(p);
+    v[0] = z[0]; v[1] = z[1]; v[2] = z[2]; v[3] = z[3];
+}
+__device__ __forceinline__ void load2(const cd *p, double v[4]) {
+    const cd a = p[0], b = p[1];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void store2(cf *p, const double v[4]) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<f4 *>(p) = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+}
+__device__ __forceinline__ void store2(cd *p, const double v[4]) {
+    p[0] = cd{v[0], v[1]};
+    p[1] = cd{v[2], v[3]};
+}
+
+// The same update with one wave per row and two columns per lane, so each
+// load and store of a wave covers a contiguous piece of the row (nvec, ldz
+// and ldr even).  Same arithmetic, in the same order, as filter_init_kernel.
+template <typename TZ>
+__global__ __launch_bounds__(256) void filter_init_rows_kernel(int64_t rows, int64_t nvec, int64_t ldz,
+                                                               int64_t ldr, TZ *Znew, const TZ *Zk,
+                                                               const TZ *Zkm, const cd *R, double beta,
+                                                               double gamma, const double *lam, double rscale) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t npair = nvec >> 1;
+    for (int64_t r = wave; r < rows; r += nwaves) {
+#pragma unroll 4
+        for (int64_t q = lane; q < npair; q += 64) {
+            const int64_t c = 2 * q, o = r * ldz + c;
+            double v[4], z[4];
+            load2(R + r * ldr + c, v);
+            const double d0 = rscale * (lam ? lam[c] : 1.0), d1 = rscale * (lam ? lam[c + 1] : 1.0);
+            v[0] *= d0; v[1] *= d0; v[2] *= d1; v[3] *= d1;
+            if (Zk) {
+                load2(Zk + o, z);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] += beta * z[i];
+            }
+            if (Zkm) {
+                load2(Zkm + o, z);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] += gamma * z[i];
+            }
+            store2(Znew + o, v);
+        }
+    }
+}
+
 static dim3 col_grid(int64_t nvec, int64_t rows, unsigned &threads) {
     threads = nvec >= 256 ? 256 : (nvec >= 128 ? 128 : 64);
     unsigned gx = (unsigned)((nvec + threads - 1) / threads);
@@ -48,6 +103,18 @@ static dim3 col_grid(int64_t nvec, int64_t rows, unsigned &threads) {
 hipError_t launch_filter_init_ld(int64_t rows, int64_t nvec, int64_t ldz, int64_t ldr, bool zf32,
                                  void *Znew, const void *Zk, const void *Zkm, const cd *R, double beta,
                                  double gamma, const double *delta, double rscale, hipStream_t s) {
+    if (nvec % 2 == 0 && ldz % 2 == 0 && ldr % 2 == 0) {
+        // 8 workgroups of 4 waves per CU; each wave strides over the rows
+        const int64_t want = (rows + 3) / 4;
+        const unsigned nb = (unsigned)(want < 2048 ? (want > 0 ? want : 1) : 2048);
+        if (zf32)
+            hipLaunchKernelGGL(filter_init_rows_kernel<cf>, dim3(nb), dim3(256), 0, s, rows, nvec, ldz, ldr,
+                               (cf *)Znew, (const cf *)Zk, (const cf *)Zkm, R, beta, gamma, delta, rscale);
+        else
+            hipLaunchKernelGGL(filter_init_rows_kernel<cd>, dim3(nb), dim3(256), 0, s, rows, nvec, ldz, ldr,
+                               (cd *)Znew, (const cd *)Zk, (const cd *)Zkm, R, beta, gamma, delta, rscale);
+        return hipGetLastError();
+    }
     unsigned th;
     dim3 g = col_grid(nvec, rows, th);
     if (zf32)
