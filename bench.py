@@ -58,7 +58,29 @@ def cpu_baseline(p, nvec=4):
                       f"projector tables included, {dt:.1f} s"}
 
 
-def converge(op, p, cfg, precs, tol, max_iter, seed=7002):
+def measured_traffic(prec, config, nvec):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated), or None when the
+    summary is for another workload or the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"cell_kernel_{prec}_{config}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("TRAFFIC "):
+                rec = json.loads(line[len("TRAFFIC "):])
+    if rec is None or rec.get("prec") != prec or rec.get("config") != config or rec.get("vectors") != nvec:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_scale"] + rec["write_kib_per_launch"] * rec["write_scale"])
+
+
+def converge(op, p, cfg, precs, tol, max_iter, seed=7002, eig_file=None):
     """Runs Algorithm RChFSI to the tolerance in each precision from the same
     start block, one iteration per library call so that progress is printed,
     and compares the wanted eigenvalues with the FP64 run."""
@@ -85,6 +107,12 @@ def converge(op, p, cfg, precs, tol, max_iter, seed=7002):
         torch.cuda.synchronize()
         res[prec] = dict(iters=it, converged=bool(out["converged"]), seconds=time.perf_counter() - t0,
                          eig=out["eigvals"].copy(), hist=hist)
+        if eig_file:
+            # every wanted eigenvalue, so runs made in separate processes can be compared
+            with open(eig_file.replace("{prec}", prec), "w") as f:
+                json.dump({"prec": prec, "tol": tol, "iterations": it, "converged": bool(out["converged"]),
+                           "seconds": res[prec]["seconds"], "residual_history": hist,
+                           "eigvals": [float(v) for v in out["eigvals"]]}, f)
         log(f"[converge] {prec}: {it} iterations, converged={out['converged']}, {res[prec]['seconds']:.1f}s")
         del X
         torch.cuda.empty_cache()
@@ -114,6 +142,9 @@ def main():
                     help="instead of timing: solve to --tol in fp64, bf16 and fp32 and compare eigenvalues")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--precs", default="fp64,bf16,fp32", help="precisions of --converge")
+    ap.add_argument("--eig-file", default=None,
+                    help="--converge: write each run's eigenvalues to this path ({prec} is replaced)")
     ap.add_argument("--hx-only", action="store_true",
                     help="only the H X products (for counter runs), after a 1 GiB fill and a 1 GiB sum that "
                          "calibrate the memory counters")
@@ -140,8 +171,8 @@ def main():
     op = binding.Chfsi(p, max_nvec=max(nsub, nhx))
     log("[bench] setup done")
     if args.converge:
-        print(json.dumps({"convergence": converge(op, p, cfg, ["fp64", "bf16", "fp32"], args.tol, args.max_iter)}),
-              flush=True)
+        print(json.dumps({"convergence": converge(op, p, cfg, args.precs.split(","), args.tol, args.max_iter,
+                                                  eig_file=args.eig_file)}), flush=True)
         return
 
     if args.hx_only:
@@ -220,7 +251,7 @@ def main():
         roof = {"bound": "hbm", "achieved": bytes_launch / t_launch / 1e9, "peak": PEAK["hbm"] / 1e9,
                 "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(pr, args.config, nhx)
     roof["kernel"] = f"cell_kernel ({pr}), avg of {launches} colour launches per H X, {nhx} vectors"
     roof["flops_per_launch"] = flops_launch
     roof["bytes_per_launch"] = bytes_launch

@@ -504,7 +504,7 @@ int rr_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, doubl
 // (Y, HY, MY) <- (.) Q.  Two Gram products and three rotations.
 // Returns CHFSI_E_NOT_SPD if the Cholesky factorisation breaks down.
 int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, double *ritz, cd *R,
-                    double *resnorm, hipStream_t s) {
+                    double *resnorm, hipStream_t s, bool rotate_hm = true) {
     const Layout &L = c->L;
     const size_t st = L.small_bytes / sizeof(cd);
     cd *Sm = c->S<cd>(L.small), *Hs = Sm + st, *T = Sm + 2 * st, *W = Sm + 3 * st, *Cm = Sm + 4 * st;
@@ -529,6 +529,22 @@ int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t l
     HIPCHK(c, launch_jacobi_eig((int)nvec, Cm, A2, V, V2, ritz, c->S<double>(L.red), 60, s, &sweeps, &Q));
     if ((rc = small_mm(c, T, Q, W, nvec, false, s))) return rc;    // W = T Q
     if ((rc = rotate(c, Y, W, nvec, ld, s))) return rc;
+    if (!rotate_hm && R) {
+        // only the residual is needed from HY and MY: R = HY W - MY (W Lambda),
+        // two products straight into R, then its column norms
+        cd *WL = Sm + 8 * st;
+        HIPCHK(c, launch_scale_cols((int)nvec, ritz, W, WL, s));
+        BLASCHK(c, rocblas_set_stream(c->blas, s));
+        const rocblas_double_complex one{1.0, 0.0}, mone{-1.0, 0.0}, zero{0.0, 0.0};
+        const rocblas_int n = (rocblas_int)nvec, rows = (rocblas_int)(2 * c->m.M), l = (rocblas_int)ld;
+        auto rb = [](const cd *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
+        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n, rows, n, &one, rb(W), n,
+                                 rb(HY), l, &zero, reinterpret_cast<rocblas_double_complex *>(R), l));
+        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, n, rows, n, &mone, rb(WL),
+                                 n, rb(MY), l, &one, reinterpret_cast<rocblas_double_complex *>(R), l));
+        if (resnorm) HIPCHK(c, launch_colnorm(2 * c->m.M, nvec, ld, R, c->S<double>(L.red), resnorm, s));
+        return CHFSI_OK;
+    }
     if ((rc = rotate(c, HY, W, nvec, ld, s))) return rc;
     if ((rc = rotate(c, MY, W, nvec, ld, s))) return rc;
     if (R || resnorm)
@@ -928,7 +944,8 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
         if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { status = rc; break; }
         HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
         rc = CHFSI_E_NOT_SPD;
-        if (o->rr_mode == 1) rc = rr_general_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s);
+        // the rotated HX and MX are not needed after the residual: it is formed from HY and MY directly
+        if (o->rr_mode == 1) rc = rr_general_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s, false);
         if (rc == CHFSI_E_NOT_SPD) {
             if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { status = rc; break; }
             rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s);

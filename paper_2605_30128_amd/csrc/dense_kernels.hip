@@ -156,6 +156,20 @@ __global__ void diag_kernel(int N, const double *scale, cd *T) {
     T[idx] = cd{i == k ? (scale ? scale[i] : 1.0) : 0.0, 0.0};
 }
 
+// B = A diag(w) for row-major N x N matrices (column j scaled by w[j])
+__global__ void scale_cols_kernel(int N, const double *w, const cd *A, cd *B) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const double f = w[idx % N];
+    B[idx] = cd{A[idx].x * f, A[idx].y * f};
+}
+
+hipError_t launch_scale_cols(int N, const double *w, const cd *A, cd *B, hipStream_t s) {
+    const int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(scale_cols_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, w, A, B);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_upper(int N, cd *A, hipStream_t s) {
     const int64_t nn = (int64_t)N * N;
     hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, A);

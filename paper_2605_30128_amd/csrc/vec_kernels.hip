@@ -242,6 +242,17 @@ __global__ void colnorm2_kernel(int64_t rows, int64_t nvec, int64_t ld, const cd
     red[(int64_t)blockIdx.y * nvec + c] = s;
 }
 
+// out[c] = ||A[:, c]||_2 (fixed-order two-stage reduction)
+hipError_t launch_colnorm(int64_t rows, int64_t nvec, int64_t ld, const cd *A, double *red, double *out,
+                          hipStream_t s) {
+    unsigned th = nvec >= 256 ? 256 : 64;
+    dim3 g((unsigned)((nvec + th - 1) / th), kRowBlocks);
+    hipLaunchKernelGGL(colnorm2_kernel, g, dim3(th), 0, s, rows, nvec, ld, A, (const double *)nullptr, red);
+    hipLaunchKernelGGL(col_finish_kernel, dim3((unsigned)((nvec + 255) / 256)), dim3(256), 0, s, red, kRowBlocks,
+                       nvec, out, 1);
+    return hipGetLastError();
+}
+
 hipError_t launch_colnorm2(int64_t rows, int64_t nvec, int64_t ld, const cd *A, const double *w,
                            double *red, double *out, hipStream_t s) {
     unsigned th = nvec >= 256 ? 256 : 64;
