@@ -375,12 +375,17 @@ int tri_inv_scaled(chfsi_ctx *c, int N, cd *L, const double *scale, cd *T, hipSt
     return CHFSI_OK;
 }
 
-// S = A^H B (N x N row-major) for [rows][ld] blocks: column-major view of a
-// row-major block is its transpose, so S^T = Bcm * Acm^H in BLAS terms.
+// S = A^H B (N x N row-major) for [rows][ld] blocks when S is Hermitian
+// (B = M A or H A).  Column-major view of a row-major block is its
+// transpose, so the upper block rows of S are S^T products Bcm Acm^H in BLAS
+// terms: one per block row of width GB, each only for the columns at and
+// right of its diagonal block (about 0.58 of the full product at N = 576).
 // The reduction dimension (2M rows) is split into nb chunks computed as one
 // strided-batched product (enough workgroups for the whole chip), the
-// partial matrices summed in a fixed order.
+// partial matrices are summed in a fixed order and the strict lower
+// triangle is filled with the conjugate of the upper one.
 int gram(chfsi_ctx *c, const cd *A, const cd *B, int64_t N, int64_t ld, cd *Sm, hipStream_t s) {
+    constexpr int64_t GB = 96;
     BLASCHK(c, rocblas_set_stream(c->blas, s));
     const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
     const int64_t rows = 2 * c->m.M;
@@ -388,30 +393,30 @@ int gram(chfsi_ctx *c, const cd *A, const cd *B, int64_t N, int64_t ld, cd *Sm, 
     int64_t nb = 32;
     while (nb > 1 && ((size_t)(nb + 1) * N * N > zcap || rows / nb < 4096)) nb /= 2;
     auto rb = [](const cd *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
-    if (nb == 1) {
-        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose,
-                                 (rocblas_int)N, (rocblas_int)N, (rocblas_int)rows, &one, rb(B), (rocblas_int)ld,
-                                 rb(A), (rocblas_int)ld, &zero, reinterpret_cast<rocblas_double_complex *>(Sm),
-                                 (rocblas_int)N));
-        return CHFSI_OK;
-    }
-    cd *part = c->S<cd>(c->L.Z);
+    auto wb = [](cd *p) { return reinterpret_cast<rocblas_double_complex *>(p); };
+    cd *part = nb == 1 ? Sm : c->S<cd>(c->L.Z);
     const int64_t chunk = rows / nb, tail = rows - nb * chunk;
-    BLASCHK(c, rocblas_zgemm_strided_batched(
-                   c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, (rocblas_int)N,
-                   (rocblas_int)N, (rocblas_int)chunk, &one, rb(B), (rocblas_int)ld, (rocblas_stride)(chunk * ld),
-                   rb(A), (rocblas_int)ld, (rocblas_stride)(chunk * ld), &zero,
-                   reinterpret_cast<rocblas_double_complex *>(part), (rocblas_int)N, (rocblas_stride)(N * N),
-                   (rocblas_int)nb));
-    int nparts = (int)nb;
-    if (tail > 0) {
-        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose,
-                                 (rocblas_int)N, (rocblas_int)N, (rocblas_int)tail, &one, rb(B + nb * chunk * ld),
-                                 (rocblas_int)ld, rb(A + nb * chunk * ld), (rocblas_int)ld, &zero,
-                                 reinterpret_cast<rocblas_double_complex *>(part + nb * N * N), (rocblas_int)N));
-        ++nparts;
+    for (int64_t i0 = 0; i0 < N; i0 += GB) {
+        const rocblas_int m = (rocblas_int)(N - i0), n = (rocblas_int)std::min(GB, N - i0);
+        if (nb == 1) {
+            BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, m, n,
+                                     (rocblas_int)rows, &one, rb(B + i0), (rocblas_int)ld, rb(A + i0),
+                                     (rocblas_int)ld, &zero, wb(part + i0 * N + i0), (rocblas_int)N));
+            continue;
+        }
+        BLASCHK(c, rocblas_zgemm_strided_batched(
+                       c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, m, n,
+                       (rocblas_int)chunk, &one, rb(B + i0), (rocblas_int)ld, (rocblas_stride)(chunk * ld),
+                       rb(A + i0), (rocblas_int)ld, (rocblas_stride)(chunk * ld), &zero, wb(part + i0 * N + i0),
+                       (rocblas_int)N, (rocblas_stride)(N * N), (rocblas_int)nb));
+        if (tail > 0)
+            BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, m, n,
+                                     (rocblas_int)tail, &one, rb(B + nb * chunk * ld + i0), (rocblas_int)ld,
+                                     rb(A + nb * chunk * ld + i0), (rocblas_int)ld, &zero,
+                                     wb(part + nb * N * N + i0 * N + i0), (rocblas_int)N));
     }
-    HIPCHK(c, launch_sum_parts(N * N, nparts, part, Sm, s));
+    if (nb > 1) HIPCHK(c, launch_sum_parts(N * N, (int)nb + (tail > 0 ? 1 : 0), part, Sm, s));
+    HIPCHK(c, launch_fill_lower(N, Sm, s));
     return CHFSI_OK;
 }
 

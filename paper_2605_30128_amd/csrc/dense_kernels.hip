@@ -170,6 +170,23 @@ hipError_t launch_scale_cols(int N, const double *w, const cd *A, cd *B, hipStre
     return hipGetLastError();
 }
 
+// strict lower triangle of a row-major N x N matrix := conjugate of the upper
+__global__ void fill_lower_kernel(int N, cd *A) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const int i = (int)(idx / N), k = (int)(idx % N);
+    if (i > k) {
+        const cd u = A[(int64_t)k * N + i];
+        A[idx] = cd{u.x, -u.y};
+    }
+}
+
+hipError_t launch_fill_lower(int N, cd *A, hipStream_t s) {
+    const int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(fill_lower_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, A);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_upper(int N, cd *A, hipStream_t s) {
     const int64_t nn = (int64_t)N * N;
     hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, A);

@@ -30,7 +30,13 @@ typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kSlice = 32;       // k per MFMA step
-constexpr int kSliceRow = 40;    // padded LDS row of a staged slice (bf16)
+constexpr int kSliceRow = 32;    // LDS row of a staged slice (bf16): one column's 32 k, four 16-byte chunks
+
+// 16-byte chunk q (k = 8q..8q+7) of column col sits at position q ^ ((col >> 2) & 3)
+// of the column's row: the 16 lanes of an MFMA B read (16 columns, one chunk)
+// and the 16 lanes of a slice store (4 columns x 4 chunks) then fall on
+// disjoint LDS banks without padding
+__device__ __forceinline__ int slice_pos(int col, int q) { return col * kSliceRow + 8 * (q ^ ((col >> 2) & 3)); }
 
 constexpr int kBfWaves = 8;                  // waves per workgroup: 4 row groups x 2 column halves
 constexpr int kBfThreads = 64 * kBfWaves;
@@ -64,7 +70,7 @@ __device__ __forceinline__ void slice_store(const u4 (&r)[Bf16Cfg<NP>::SITER], _
 #pragma unroll
     for (int u = 0; u < C::SITER; ++u) {
         const int c = threadIdx.x + u * kBfThreads;
-        if (c < C::CHUNKS) *reinterpret_cast<u4 *>(bs + (c >> 2) * kSliceRow + 8 * (c & 3)) = r[u];
+        if (c < C::CHUNKS) *reinterpret_cast<u4 *>(bs + slice_pos(c >> 2, c & 3)) = r[u];
     }
 }
 
@@ -82,7 +88,7 @@ __device__ __forceinline__ void slice_mfma(f4 (*acc)[Bf16Cfg<NP>::NTW], const __
         a[mm] = *reinterpret_cast<const bf8 *>(as + (16 * (mh * MH + mm) + cn) * KS + s * kSlice + kq);
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
-        const bf8 b = *reinterpret_cast<const bf8 *>(cur + (16 * (nt0 + t) + cn) * kSliceRow + kq);
+        const bf8 b = *reinterpret_cast<const bf8 *>(cur + slice_pos(16 * (nt0 + t) + cn, kq >> 3));
 #pragma unroll
         for (int mm = 0; mm < MH; ++mm)
             acc[mm][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mm], b, acc[mm][t], 0, 0, 0);
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a) {
                     __syncthreads();
 #pragma unroll
                     for (int t = 0; t < NTW; ++t) {
-                        const bf8 bv = *reinterpret_cast<const bf8 *>(bs + (16 * (nt0 + t) + cn) * kSliceRow + kq);
+                        const bf8 bv = *reinterpret_cast<const bf8 *>(bs + slice_pos(16 * (nt0 + t) + cn, kq >> 3));
 #pragma unroll
                         for (int mm = 0; mm < MH; ++mm)
                             tq[mm][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mm], bv, tq[mm][t], 0, 0, 0);

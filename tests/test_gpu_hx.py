@@ -99,6 +99,23 @@ def test_hx_bf16_tiny(B, tiny):
     assert np.all(Yr[:, 21:] == 0)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16", 2e-2)])
+def test_hx_odd_ld(B, tiny, prec, tol):
+    """An odd leading dimension (rows not 16-byte aligned) and an odd column
+    count: the kernels fall back to element-wise access at row ends and the
+    columns past nvec stay untouched."""
+    p, o = tiny
+    X = synth.random_block(p.ndof, 19, 111, ld=23)
+    ref = o.apply_H(X[:, :19])
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    op = B.Chfsi(p, max_nvec=32)
+    Yd = _dev(np.full((p.ndof, 23), 5.0 - 1.0j), dt)
+    op.apply_H(_dev(X, dt), prec=prec, nvec=19, Y=Yd)
+    Y = Yd.cpu().numpy()
+    assert _rel(Y[:, :19], ref) < tol
+    assert np.all(Y[:, 19:] == 5.0 - 1.0j)
+
+
 @pytest.mark.parametrize("deg,ncell,soc", [(1, (2, 2, 2), False), (2, (2, 2, 4), True), (3, (2, 2, 2), True),
                                            (5, (2, 2, 2), True), (6, (2, 2, 2), True), (7, (2, 2, 2), False)])
 def test_hx_all_degrees(B, oracle_lib, deg, ncell, soc):
