@@ -58,6 +58,39 @@ def cpu_baseline(p, nvec=4):
                       f"projector tables included, {dt:.1f} s"}
 
 
+def bfp_throughput(n=1 << 28, reps=5):
+    """Device-event throughput of the block floating-point codec on n float
+    values (1 GiB), per rate: bytes moved (floats and stream, read + write)
+    per second and the fraction of the 8 TB/s HBM peak."""
+    import torch
+
+    from paper_2605_30128_amd import binding
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randn(n, generator=g, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    out = {}
+    for nbits in (16, 12, 10):
+        s = binding.bfp_encode(x, nbits)
+        binding.bfp_decode(s, n, nbits, out=y)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for _ in range(reps):
+            binding.bfp_encode(x, nbits, out=s)
+        ev[1].record()
+        for _ in range(reps):
+            binding.bfp_decode(s, n, nbits, out=y)
+        ev[2].record()
+        torch.cuda.synchronize()
+        moved = 4 * n + s.numel()
+        te, td = ev[0].elapsed_time(ev[1]) / reps * 1e-3, ev[1].elapsed_time(ev[2]) / reps * 1e-3
+        out[f"bfp{nbits}"] = {"encode_GBps": moved / te / 1e9, "decode_GBps": moved / td / 1e9,
+                              "encode_frac_hbm": moved / te / PEAK["hbm"], "decode_frac_hbm": moved / td / PEAK["hbm"]}
+        del s
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def measured_traffic(prec, config, nvec):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, calibrated), or None when the
@@ -257,6 +290,10 @@ def main():
     roof["bytes_per_launch"] = bytes_launch
     roof["ms_per_launch"] = t_launch * 1e3
 
+    bfp = bfp_throughput()
+    log(f"[bench] bfp codec: " + ", ".join(f"{k} enc {v['encode_GBps']:.0f} / dec {v['decode_GBps']:.0f} GB/s"
+                                           for k, v in bfp.items()))
+
     cpu = None
     if not args.no_cpu_baseline:
         try:
@@ -291,6 +328,7 @@ def main():
         "hx_gdofvec_per_s": hx,
         "hx_profile_ms": prof,
         "roofline": roof,
+        "bfp_codec": bfp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -256,6 +256,26 @@ int chfsi_info(const chfsi_ctx *ctx, int64_t *nnodes, int64_t *ncells, int *n, i
 /* The diagonal D (GLL-integrated mass, Sec. III-B2) as double device [M]. */
 int chfsi_mass_diag(chfsi_ctx *ctx, double *D, void *stream);
 
+/* Block floating-point codec (Sec. III-C4, compressed communication, fig.
+ * layout).  Four float values form one block of N_bits = 4*nbits bits,
+ * nbits in {16, 12, 10}: the low 8 bits hold the shared biased exponent
+ * e = e_max + 127 with 2^(e_max-1) <= max|x_i| < 2^e_max (e_max >= -126; 0
+ * marks an all-zero block), then four signed coefficients of
+ * v = nbits - 2 bits (x_0 first), q_i = round(x_i 2^(v-1-e_max)) with ties
+ * to even, clamped to 2^(v-1) - 1 above, stored as their low v bits in two's
+ * complement.  Decoding returns q_i 2^(e_max-v+1) exactly.  Blocks are
+ * little-endian and back to back, nbits/2 bytes each, so a stream of n
+ * values takes n/4 * nbits/2 bytes and block b depends only on x[4b..4b+3].
+ * n must be a multiple of 4 and the values finite.  x is 16-byte aligned;
+ * the stream is aligned to 8 (nbits 16), 2 (12) or 1 (10) bytes.  Device
+ * buffers owned by the caller; stream-ordered; these functions take no
+ * context: on failure the message is chfsi_last_error(NULL).
+ * Returns CHFSI_E_ARG for a bad nbits, n, NULL or misaligned buffer,
+ * CHFSI_E_DEVICE if the launch fails. */
+int chfsi_bfp_bytes(int nbits, int64_t n, int64_t *bytes);
+int chfsi_bfp_encode(int nbits, const float *x, int64_t n, void *out, void *stream);
+int chfsi_bfp_decode(int nbits, const void *in, int64_t n, float *x, void *stream);
+
 const char *chfsi_last_error(const chfsi_ctx *ctx);
 void chfsi_destroy(chfsi_ctx *ctx);
 

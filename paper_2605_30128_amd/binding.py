@@ -56,7 +56,8 @@ SYMBOLS = [
     "chfsi_plan", "chfsi_setup", "chfsi_set_fields", "chfsi_apply_H", "chfsi_apply_M",
     "chfsi_apply_H_adjoint", "chfsi_estimate_bounds", "chfsi_filter", "chfsi_orthonormalize",
     "chfsi_rayleigh_ritz", "chfsi_rayleigh_ritz_general", "chfsi_residual", "chfsi_solve_workspace", "chfsi_solve", "chfsi_info",
-    "chfsi_mass_diag", "chfsi_profile_apply_H", "chfsi_last_error", "chfsi_destroy",
+    "chfsi_mass_diag", "chfsi_profile_apply_H", "chfsi_bfp_bytes", "chfsi_bfp_encode", "chfsi_bfp_decode",
+    "chfsi_last_error", "chfsi_destroy",
 ]
 
 _lib = None
@@ -88,6 +89,9 @@ def load(path: str = LIB_PATH):
     L.chfsi_info.argtypes = [vp, vp, vp, vp, vp]
     L.chfsi_mass_diag.argtypes = [vp, vp, vp]
     L.chfsi_profile_apply_H.argtypes = [vp, i, vp, vp, i64, i64, vp, vp, vp]
+    L.chfsi_bfp_bytes.argtypes = [i, i64, vp]
+    L.chfsi_bfp_encode.argtypes = [i, vp, i64, vp, vp]
+    L.chfsi_bfp_decode.argtypes = [i, vp, i64, vp, vp]
     L.chfsi_last_error.argtypes = [vp]
     L.chfsi_last_error.restype = C.c_char_p
     L.chfsi_destroy.argtypes = [vp]
@@ -109,6 +113,39 @@ def _stream():
 
 def cplx_dtype(prec) -> torch.dtype:
     return torch.complex128 if PREC[prec] == FP64 else torch.complex64
+
+
+def _check_global(rc):
+    if rc < 0:
+        raise ChfsiError(rc, load().chfsi_last_error(None).decode())
+    return rc
+
+
+def bfp_bytes(nbits: int, n: int) -> int:
+    """Size in bytes of the block floating-point stream of n values."""
+    out = C.c_int64()
+    _check_global(load().chfsi_bfp_bytes(int(nbits), int(n), C.byref(out)))
+    return out.value
+
+
+def bfp_encode(x, nbits: int, out=None):
+    """Encodes a contiguous float32 device tensor (numel a multiple of 4)
+    into a uint8 device tensor (chfsi_bfp_encode)."""
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 tensor")
+    n = x.numel()
+    if out is None:
+        out = torch.empty(bfp_bytes(nbits, n), dtype=torch.uint8, device=x.device)
+    _check_global(load().chfsi_bfp_encode(int(nbits), _ptr(x), n, _ptr(out), _stream()))
+    return out
+
+
+def bfp_decode(stream, n: int, nbits: int, out=None):
+    """Decodes n float32 values from a uint8 device stream (chfsi_bfp_decode)."""
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=stream.device)
+    _check_global(load().chfsi_bfp_decode(int(nbits), _ptr(stream), int(n), _ptr(out), _stream()))
+    return out
 
 
 @dataclass

@@ -1039,6 +1039,38 @@ int chfsi_mass_diag(chfsi_ctx *c, double *D, void *stream) {
     return CHFSI_OK;
 }
 
+int chfsi_bfp_bytes(int nbits, int64_t n, int64_t *bytes) {
+    if (nbits != 16 && nbits != 12 && nbits != 10) return fail(nullptr, CHFSI_E_ARG, "nbits must be 16, 12 or 10");
+    if (n < 0 || n % 4) return fail(nullptr, CHFSI_E_ARG, "n must be a non-negative multiple of 4");
+    if (!bytes) return fail(nullptr, CHFSI_E_ARG, "bytes is NULL");
+    *bytes = n / 4 * (nbits / 2);
+    return CHFSI_OK;
+}
+
+static int bfp_call(bool enc, int nbits, const void *src, int64_t n, void *dst, void *stream) {
+    int64_t nbytes = 0;
+    int rc = chfsi_bfp_bytes(nbits, n, &nbytes);
+    if (rc) return rc;
+    if (n == 0) return CHFSI_OK;
+    if (!src || !dst) return fail(nullptr, CHFSI_E_ARG, "NULL buffer");
+    const void *f = enc ? src : (const void *)dst;
+    const void *b = enc ? (const void *)dst : src;
+    const uintptr_t balign = nbits == 16 ? 8 : (nbits == 12 ? 2 : 1);
+    if ((reinterpret_cast<uintptr_t>(f) & 15) || (reinterpret_cast<uintptr_t>(b) & (balign - 1)))
+        return fail(nullptr, CHFSI_E_ARG, "float buffer must be 16-byte aligned, stream aligned to its store width");
+    hipError_t e = launch_bfp(enc, nbits, src, n, dst, S(stream));
+    if (e != hipSuccess) return fail(nullptr, CHFSI_E_DEVICE, std::string("bfp kernel: ") + hipGetErrorString(e));
+    return CHFSI_OK;
+}
+
+int chfsi_bfp_encode(int nbits, const float *x, int64_t n, void *out, void *stream) {
+    return bfp_call(true, nbits, x, n, out, stream);
+}
+
+int chfsi_bfp_decode(int nbits, const void *in, int64_t n, float *x, void *stream) {
+    return bfp_call(false, nbits, in, n, x, stream);
+}
+
 const char *chfsi_last_error(const chfsi_ctx *c) {
     if (c) return c->err.c_str();
     return g_err.c_str();

@@ -95,3 +95,22 @@ def test_null_context_calls_fail_cleanly(lib):
     assert L.chfsi_filter(None, 0, 5, None, None, None, None, None, 1, 1, None) == binding.E_ARG
     assert L.chfsi_solve(None, 1, None, None, 2, 2, None, None, None, None, None, 0, None) == binding.E_ARG
     L.chfsi_destroy(None)
+
+
+def test_bfp_sizes_and_argument_checks(lib):
+    """The codec entry points size the stream and reject bad arguments
+    before any device work (an empty stream launches nothing)."""
+    from paper_2605_30128_amd import binding
+    L = binding.load()
+    out = C.c_int64()
+    for nbits, per4 in ((16, 8), (12, 6), (10, 5)):
+        assert L.chfsi_bfp_bytes(nbits, 4096, C.byref(out)) == 0
+        assert out.value == 1024 * per4
+    assert L.chfsi_bfp_bytes(14, 8, C.byref(out)) == -1
+    assert L.chfsi_bfp_bytes(16, 6, C.byref(out)) == -1
+    assert L.chfsi_bfp_bytes(16, -4, C.byref(out)) == -1
+    assert L.chfsi_bfp_encode(16, None, 0, None, None) == 0
+    assert L.chfsi_bfp_decode(12, None, 0, None, None) == 0
+    assert L.chfsi_bfp_encode(16, None, 8, None, None) == -1
+    assert L.chfsi_bfp_decode(10, None, 4, None, None) == -1
+    assert b"NULL" in L.chfsi_last_error(None)
