@@ -113,7 +113,7 @@ def measured_traffic(prec, config, nvec):
     return 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_scale"] + rec["write_kib_per_launch"] * rec["write_scale"])
 
 
-def converge(op, p, cfg, precs, tol, max_iter, seed=7002, eig_file=None):
+def converge(op, p, cfg, precs, tol, max_iter, seed=7002, eig_file=None, rr_mode=1):
     """Runs Algorithm RChFSI to the tolerance in each precision from the same
     start block, one iteration per library call so that progress is printed,
     and compares the wanted eigenvalues with the FP64 run."""
@@ -126,13 +126,15 @@ def converge(op, p, cfg, precs, tol, max_iter, seed=7002, eig_file=None):
     v0 = torch.from_numpy(synth.random_block(p.ndof, 1, seed + 1)[:, 0])
     res = {}
     for prec in precs:
+        rrm = rr_mode if prec != "fp64" else 1  # the FP64 reference keeps the FP64 rotation
         X = torch.from_numpy(X0).to("cuda", torch.complex128)
         t0 = time.perf_counter()
-        out = op.solve(X, nw, q, prec=prec, tol=tol, max_iter=1, v0=v0)
+        out = op.solve(X, nw, q, prec=prec, tol=tol, max_iter=1, v0=v0, rr_mode=rrm)
         lmax, work, hist = out["bounds"][2], out["work"], [float(out["hist_res"][0])]
         it = 1
         while not out["converged"] and it < max_iter:
-            out = op.solve(X, nw, q, prec=prec, tol=tol, max_iter=1, resume=True, work=work, lambda_max=lmax)
+            out = op.solve(X, nw, q, prec=prec, tol=tol, max_iter=1, resume=True, work=work, lambda_max=lmax,
+                           rr_mode=rrm)
             hist.append(float(out["max_res"]))
             it += 1
             log(f"[converge] {prec} iteration {it}: max residual {out['max_res']:.3e} "
@@ -176,6 +178,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=60)
     ap.add_argument("--precs", default="fp64,bf16,fp32", help="precisions of --converge")
+    ap.add_argument("--rr-mode", type=int, default=2, choices=[0, 1, 2],
+                    help="Rayleigh-Ritz of the mixed iterations: 1 FP64, 2 mixed-precision subspace rotation")
     ap.add_argument("--eig-file", default=None,
                     help="--converge: write each run's eigenvalues to this path ({prec} is replaced)")
     ap.add_argument("--hx-only", action="store_true",
@@ -205,7 +209,7 @@ def main():
     log("[bench] setup done")
     if args.converge:
         print(json.dumps({"convergence": converge(op, p, cfg, args.precs.split(","), args.tol, args.max_iter,
-                                                  eig_file=args.eig_file)}), flush=True)
+                                                  eig_file=args.eig_file, rr_mode=args.rr_mode)}), flush=True)
         return
 
     if args.hx_only:
@@ -244,14 +248,15 @@ def main():
     n_wanted = cfg["n_wanted"]
     X = torch.from_numpy(synth.random_block(p.ndof, nsub, 7002)).to("cuda", torch.complex128)
     v0 = torch.from_numpy(synth.random_block(p.ndof, 1, 7003)[:, 0])
-    out = op.solve(X, n_wanted, q, prec=args.prec, max_iter=max(args.warmup, 1), fixed_iters=True, v0=v0)
+    out = op.solve(X, n_wanted, q, prec=args.prec, max_iter=max(args.warmup, 1), fixed_iters=True, v0=v0,
+                   rr_mode=args.rr_mode)
     lmax = out["bounds"][2]
     work = out["work"]
     log(f"[bench] warmup done: residual {out['max_res']:.3e}, lambda_max {lmax:.3f}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = op.solve(X, n_wanted, q, prec=args.prec, max_iter=args.steps, fixed_iters=True, resume=True, work=work,
-                   lambda_max=lmax)
+                   lambda_max=lmax, rr_mode=args.rr_mode)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall / args.steps * 1e3
@@ -263,7 +268,7 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         o64 = op.solve(X, n_wanted, q, prec="fp64", max_iter=1, fixed_iters=True, resume=True, work=work,
-                       lambda_max=lmax)
+                       lambda_max=lmax, rr_mode=1)
         torch.cuda.synchronize()
         it64 = time.perf_counter() - t1
         log(f"[bench] 1 fp64 iteration: {it64 * 1e3:.1f} ms (filter {o64['t_filter']:.3f}s)")
@@ -320,7 +325,7 @@ def main():
                         f"cells, p={p.degree}, {p.ndof} complex spinor dofs, {p.natoms} atoms x {p.nbeta} SOC "
                         f"projectors, {nsub}-column subspace ({n_wanted} wanted), Chebyshev degree {q}",
             "filter_precision": pr,
-            "rr_precision": "fp64",
+            "rr_precision": "fp64" if args.rr_mode < 2 else "fp64 (subspace rotation fp64 diagonal / fp32 off-diagonal blocks)",
             "hx_vectors": nhx,
             "nsub": nsub,
         },

@@ -207,7 +207,13 @@ typedef struct {
                            chfsi_rayleigh_ritz); 1: Rayleigh-Ritz of the
                            generalized subspace problem through one Cholesky
                            factor of Y^H M Y (chfsi_rayleigh_ritz_general),
-                           falling back to mode 0 on a Cholesky breakdown */
+                           falling back to mode 0 on a Cholesky breakdown;
+                           2: as 1 with the paper's mixed-precision subspace
+                           rotation (Sec. III-C5, RR-SR): X <- Y Q with the
+                           diagonal 64 x 64 blocks of Q in FP64 and the rest
+                           in FP32 (complex64 copies, FP32 MFMA), summed in
+                           FP64; the residual products stay FP64.
+                           Other values: CHFSI_E_ARG */
     int resume;         /* if != 0, X and the workspace hold the state left by
                            a previous chfsi_solve on the same X and workspace
                            (Ritz vectors, HX, MX, R, Ritz values): the initial

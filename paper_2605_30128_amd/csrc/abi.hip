@@ -450,6 +450,44 @@ int rotate(chfsi_ctx *c, cd *A, const cd *Q, int64_t N, int64_t ld, hipStream_t 
     return CHFSI_OK;
 }
 
+// A <- A Q with the paper's mixed-precision subspace rotation (RR-SR, Sec.
+// III-C5 on the Rayleigh-Ritz step): the diagonal SRB x SRB blocks of Q in
+// FP64 (one strided-batched zgemm), the off-diagonal part in FP32 (cgemm on
+// complex64 copies of A and of Q with its diagonal blocks zeroed), summed in
+// FP64.  Q32 is scratch for an N x N complex64 matrix.
+constexpr int64_t SRB = 64;
+int rotate_mixed(chfsi_ctx *c, cd *A, const cd *Q, int64_t N, int64_t ld, cf *Q32, hipStream_t s) {
+    const int64_t rows = 2 * c->m.M;
+    cd *T = c->S<cd>(c->L.Z);
+    cf *A32 = reinterpret_cast<cf *>(T + rows * N), *C32 = A32 + rows * N;
+    BLASCHK(c, rocblas_set_stream(c->blas, s));
+    const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
+    const rocblas_float_complex onef{1.0f, 0.0f}, zerof{0.0f, 0.0f};
+    auto zc = [](const cd *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
+    const int64_t nfull = N / SRB, rem = N - nfull * SRB;
+    if (nfull > 0)
+        BLASCHK(c, rocblas_zgemm_strided_batched(
+                       c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)SRB, (rocblas_int)rows,
+                       (rocblas_int)SRB, &one, zc(Q), (rocblas_int)N, (rocblas_stride)(SRB * (N + 1)), zc(A),
+                       (rocblas_int)ld, (rocblas_stride)SRB, &zero, reinterpret_cast<rocblas_double_complex *>(T),
+                       (rocblas_int)N, (rocblas_stride)SRB, (rocblas_int)nfull));
+    if (rem > 0) {
+        const int64_t o = nfull * SRB;
+        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)rem,
+                                 (rocblas_int)rows, (rocblas_int)rem, &one, zc(Q + o * N + o), (rocblas_int)N,
+                                 zc(A + o), (rocblas_int)ld, &zero, reinterpret_cast<rocblas_double_complex *>(T + o),
+                                 (rocblas_int)N));
+    }
+    HIPCHK(c, launch_offdiag_cf((int)N, (int)SRB, Q, Q32, s));
+    HIPCHK(c, launch_sr_to_cf(rows, N, ld, A, A32, s));
+    BLASCHK(c, rocblas_cgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)rows,
+                             (rocblas_int)N, &onef, reinterpret_cast<const rocblas_float_complex *>(Q32), (rocblas_int)N,
+                             reinterpret_cast<const rocblas_float_complex *>(A32), (rocblas_int)N, &zerof,
+                             reinterpret_cast<rocblas_float_complex *>(C32), (rocblas_int)N));
+    HIPCHK(c, launch_sr_combine(rows, N, ld, T, C32, A, s));
+    return CHFSI_OK;
+}
+
 int apply_H_impl(chfsi_ctx *c, chfsi_prec prec, const void *X, void *Y, int64_t nvec, int64_t ld,
                  hipStream_t s) {
     const int nl = c->m.npairs > 0 ? FLAG_NLOC : 0;
@@ -509,7 +547,7 @@ int rr_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, doubl
 // (Y, HY, MY) <- (.) Q.  Two Gram products and three rotations.
 // Returns CHFSI_E_NOT_SPD if the Cholesky factorisation breaks down.
 int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, double *ritz, cd *R,
-                    double *resnorm, hipStream_t s, bool rotate_hm = true) {
+                    double *resnorm, hipStream_t s, bool rotate_hm = true, bool mixed_sr = false) {
     const Layout &L = c->L;
     const size_t st = L.small_bytes / sizeof(cd);
     cd *Sm = c->S<cd>(L.small), *Hs = Sm + st, *T = Sm + 2 * st, *W = Sm + 3 * st, *Cm = Sm + 4 * st;
@@ -533,7 +571,11 @@ int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t l
     int sweeps = 0;
     HIPCHK(c, launch_jacobi_eig((int)nvec, Cm, A2, V, V2, ritz, c->S<double>(L.red), 60, s, &sweeps, &Q));
     if ((rc = small_mm(c, T, Q, W, nvec, false, s))) return rc;    // W = T Q
-    if ((rc = rotate(c, Y, W, nvec, ld, s))) return rc;
+    if (mixed_sr) {
+        if ((rc = rotate_mixed(c, Y, W, nvec, ld, reinterpret_cast<cf *>(A2), s))) return rc;
+    } else if ((rc = rotate(c, Y, W, nvec, ld, s))) {
+        return rc;
+    }
     if (!rotate_hm && R) {
         // only the residual is needed from HY and MY: R = HY W - MY (W Lambda),
         // two products straight into R, then its column norms
@@ -890,6 +932,7 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
     if (nsub < 2) return fail(c, CHFSI_E_ARG, "nsub must be >= 2");
     if (o->degree < 1 || o->degree > kMaxDegree || o->max_iter < 1) return fail(c, CHFSI_E_ARG, "bad degree or max_iter");
     if (o->prec < CHFSI_FP64 || o->prec > CHFSI_BF16) return fail(c, CHFSI_E_ARG, "unknown precision");
+    if (o->rr_mode < 0 || o->rr_mode > 2) return fail(c, CHFSI_E_ARG, "rr_mode must be 0, 1 or 2");
     if (!eigvals) return fail(c, CHFSI_E_ARG, "eigvals is NULL");
     size_t need = 0;
     if ((rc = chfsi_solve_workspace(c, nsub, ld, &need))) return rc;
@@ -950,7 +993,7 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
         HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
         rc = CHFSI_E_NOT_SPD;
         // the rotated HX and MX are not needed after the residual: it is formed from HY and MY directly
-        if (o->rr_mode == 1) rc = rr_general_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s, false);
+        if (o->rr_mode >= 1) rc = rr_general_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s, false, o->rr_mode == 2);
         if (rc == CHFSI_E_NOT_SPD) {
             if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { status = rc; break; }
             rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s);

@@ -187,6 +187,21 @@ hipError_t launch_fill_lower(int N, cd *A, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Q32 = complex64 copy of the N x N matrix Q with its diagonal bs x bs blocks zeroed
+__global__ void offdiag_cf_kernel(int N, int bs, const cd *Q, cf *Q32) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const int i = (int)(idx / N), k = (int)(idx % N);
+    const cd q = Q[idx];
+    Q32[idx] = (i / bs == k / bs) ? cf{0.f, 0.f} : cf{(float)q.x, (float)q.y};
+}
+
+hipError_t launch_offdiag_cf(int N, int bs, const cd *Q, cf *Q32, hipStream_t s) {
+    const int64_t nn = (int64_t)N * N;
+    hipLaunchKernelGGL(offdiag_cf_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, bs, Q, Q32);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_upper(int N, cd *A, hipStream_t s) {
     const int64_t nn = (int64_t)N * N;
     hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, N, A);

@@ -139,6 +139,9 @@ hipError_t launch_herm_equilibrate(int N, cd *S, double *scale, int *flag, hipSt
 hipError_t launch_hermitize(int N, cd *S, hipStream_t s);
 hipError_t launch_cholesky_block(int n, int lda, cd *A, int *flag, hipStream_t s);
 hipError_t launch_zero_upper(int N, cd *A, hipStream_t s);
+hipError_t launch_offdiag_cf(int N, int bs, const cd *Q, cf *Q32, hipStream_t s);
+hipError_t launch_sr_to_cf(int64_t rows, int64_t N, int64_t ld, const cd *A, cf *A32, hipStream_t s);
+hipError_t launch_sr_combine(int64_t rows, int64_t N, int64_t ld, const cd *T, const cf *C32, cd *A, hipStream_t s);
 // block floating-point codec: encode (enc) float[n] -> stream, or decode stream -> float[n]
 hipError_t launch_bfp(bool enc, int nbits, const void *src, int64_t n, void *dst, hipStream_t s);
 hipError_t launch_fill_lower(int N, cd *A, hipStream_t s);

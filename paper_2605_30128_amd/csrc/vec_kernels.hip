@@ -276,6 +276,41 @@ __global__ void cast_kernel(int64_t rows, int64_t nvec, int64_t ld, const TS *sr
     }
 }
 
+// Mixed-precision subspace rotation helpers: A32[r][c] = (complex64) A[r*ld + c]
+// (compact rows of N), and A[r*ld + c] = T[r][c] + C32[r][c] (T compact complex128).
+__global__ void sr_to_cf_kernel(int64_t rows, int64_t N, int64_t ld, const cd *A, cf *A32) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const cd v = A[r * ld + c];
+        A32[r * N + c] = cf{(float)v.x, (float)v.y};
+    }
+}
+
+__global__ void sr_combine_kernel(int64_t rows, int64_t N, int64_t ld, const cd *T, const cf *C32, cd *A) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const cd t = T[r * N + c];
+        const cf u = C32[r * N + c];
+        A[r * ld + c] = cd{t.x + (double)u.x, t.y + (double)u.y};
+    }
+}
+
+hipError_t launch_sr_to_cf(int64_t rows, int64_t N, int64_t ld, const cd *A, cf *A32, hipStream_t s) {
+    unsigned th;
+    dim3 g = col_grid(N, rows, th);
+    hipLaunchKernelGGL(sr_to_cf_kernel, g, dim3(th), 0, s, rows, N, ld, A, A32);
+    return hipGetLastError();
+}
+
+hipError_t launch_sr_combine(int64_t rows, int64_t N, int64_t ld, const cd *T, const cf *C32, cd *A, hipStream_t s) {
+    unsigned th;
+    dim3 g = col_grid(N, rows, th);
+    hipLaunchKernelGGL(sr_combine_kernel, g, dim3(th), 0, s, rows, N, ld, T, C32, A);
+    return hipGetLastError();
+}
+
 hipError_t launch_cast_block(int64_t rows, int64_t nvec, int64_t ld, const void *src, bool src32,
                              void *dst, bool dst32, hipStream_t s) {
     unsigned th;

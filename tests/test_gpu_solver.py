@@ -145,6 +145,24 @@ def test_solve_tiny_fp64_matches_golden(B, rr_mode):
     assert np.abs(out["eigvals"] - ref).max() < 1e-10, np.abs(out["eigvals"] - ref).max()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_solve_mixed_subspace_rotation(B, prec):
+    """rr_mode 2 (FP32 off-diagonal blocks of the subspace rotation) with a
+    subspace of 144 columns (two full 64-column blocks and a 16-column tail):
+    converges to tol and its lowest eigenvalues match the oracle's golden
+    values as closely as the FP64 rotation does."""
+    g = json.load(open(GOLD))
+    p = synth.make_config("tiny")
+    op = B.Chfsi(p, max_nvec=144)
+    X = _dev(synth.random_block(p.ndof, 144, 2101))
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, g["lanczos_seed"])[:, 0])
+    out = op.solve(X, 128, g["degree"], prec=prec, tol=1e-8, max_iter=300, v0=v0, rr_mode=2)
+    print(prec, "iterations", out["iters"], "max residual", out["max_res"])
+    assert out["converged"], out
+    ref = np.asarray(g["eigenvalues"][:g["n_wanted"]])
+    assert np.abs(out["eigvals"][:g["n_wanted"]] - ref).max() < 1e-9
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_solve_tiny_mixed(B, prec):
     g = json.load(open(GOLD))
