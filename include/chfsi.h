@@ -282,6 +282,63 @@ int chfsi_bfp_bytes(int nbits, int64_t n, int64_t *bytes);
 int chfsi_bfp_encode(int nbits, const float *x, int64_t n, void *out, void *stream);
 int chfsi_bfp_decode(int nbits, const void *in, int64_t n, float *x, void *stream);
 
+/* ------------------------------------------------------------------ Poisson
+ * The FE-discretized Poisson problem K V = f of the electrostatics (Sec.
+ * III-B1): K_IJ = sum_e int_e grad N_I . grad N_J on the context's periodic
+ * mesh, with the same nodes and Gauss quadrature as H.  Vectors are double
+ * device arrays [M], node index gx + Nx (gy + Ny gz), owned by the caller.
+ * K is assembled matrix-free and sum-factorised (Sec. III-B1, the Kx kernel
+ * paragraph: extraction, 1D contractions, Jacobian and assembly in one
+ * launch); it needs nq1d = degree + 1 or degree + 2 (else CHFSI_E_ARG).  K
+ * is symmetric positive semi-definite; its null space is the constants. */
+
+/* y = K x.  x and y must not overlap (y is zeroed first, then assembled with
+ * atomic adds, so the last bits of y may differ between calls). */
+int chfsi_apply_K(chfsi_ctx *ctx, const double *x, double *y, void *stream);
+
+/* Chebyshev-Jacobi preconditioner of the PCG section: z = P^{-1} r with
+ * P^{-1} = chi(D^{-1} K) D^{-1}, D = diag(K), chi the degree-m Chebyshev
+ * approximation of 1/lambda on [lmin, lmax] (m steps of the Chebyshev
+ * iteration on D^{-1} K z = D^{-1} r from z = 0, m - 1 applications of K;
+ * m = 1 is Jacobi scaled by 2/(lmin+lmax)).  0 < lmin < lmax finite,
+ * 1 <= degree <= 64; r and z must not overlap. */
+int chfsi_poisson_precond(chfsi_ctx *ctx, int degree, double lmin, double lmax, const double *r,
+                          double *z, void *stream);
+
+typedef struct {
+    double tol;          /* absolute: stop once ||K x - f'||_2 < tol (f' below) */
+    int max_iter;        /* >= 0 */
+    int cheb_degree;     /* preconditioner degree m, 1..64 */
+    int lanczos_steps;   /* steps of the spectral estimate (when lambda_max == 0), 1..1000 */
+    double lambda_max;   /* > 0: upper bound of the spectrum of D^{-1} K to use; 0: estimate */
+    double range;        /* lmin = lambda_max / range, range > 1 */
+} chfsi_pcg_opts;
+
+typedef struct {
+    int iters;           /* PCG iterations taken */
+    int converged;
+    double res_norm;     /* ||r||_2 of the recurrence residual at exit */
+    double lambda_min, lambda_max; /* preconditioner interval used */
+    double t_lanczos, t_total;     /* seconds (host clock around synchronized work) */
+} chfsi_pcg_report;
+
+/* Solves K x = f' with f' = f - mean(f) (the part of f in the range of K) by
+ * the PCG of Algorithm pcg_fusion: w = K p; eta = p.w; alpha = delta/eta;
+ * x += alpha p and r += alpha w in one pass; z = P^{-1} r; (delta_new,
+ * gamma) = (r.z, r.r) in one reduction; beta = delta_new/delta; p = -z +
+ * beta p; stop when sqrt(gamma) < tol.  r = K x - f' starts from the
+ * caller's x (initial guess, e.g. the previous SCF step's potential), and
+ * delta, eta, beta live in device memory: the host reads gamma once per
+ * iteration.  Without opts->lambda_max the upper bound comes from a
+ * Lanczos run on D^{-1/2} K D^{-1/2} (theta_max + |beta_k|) from a fixed
+ * splitmix64 start vector.  On return x holds the zero-mean solution (the
+ * constant mode is removed).  f and x must not overlap.  Returns CHFSI_OK,
+ * CHFSI_NOT_CONVERGED after max_iter iterations (x holds the last iterate),
+ * CHFSI_E_NONFINITE on a non-finite or non-positive curvature p.w, or
+ * CHFSI_E_ARG.  Synchronizes the stream. */
+int chfsi_poisson_solve(chfsi_ctx *ctx, const chfsi_pcg_opts *opts, const double *f, double *x,
+                        chfsi_pcg_report *report, void *stream);
+
 const char *chfsi_last_error(const chfsi_ctx *ctx);
 void chfsi_destroy(chfsi_ctx *ctx);
 

@@ -52,11 +52,23 @@ class Report(C.Structure):
                 ("t_total", C.c_double), ("t_iter_median", C.c_double)]
 
 
+class PcgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("cheb_degree", C.c_int),
+                ("lanczos_steps", C.c_int), ("lambda_max", C.c_double), ("range", C.c_double)]
+
+
+class PcgReport(C.Structure):
+    _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("res_norm", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("t_lanczos", C.c_double),
+                ("t_total", C.c_double)]
+
+
 SYMBOLS = [
     "chfsi_plan", "chfsi_setup", "chfsi_set_fields", "chfsi_apply_H", "chfsi_apply_M",
     "chfsi_apply_H_adjoint", "chfsi_estimate_bounds", "chfsi_filter", "chfsi_orthonormalize",
     "chfsi_rayleigh_ritz", "chfsi_rayleigh_ritz_general", "chfsi_residual", "chfsi_solve_workspace", "chfsi_solve", "chfsi_info",
     "chfsi_mass_diag", "chfsi_profile_apply_H", "chfsi_bfp_bytes", "chfsi_bfp_encode", "chfsi_bfp_decode",
+    "chfsi_apply_K", "chfsi_poisson_precond", "chfsi_poisson_solve",
     "chfsi_last_error", "chfsi_destroy",
 ]
 
@@ -92,6 +104,9 @@ def load(path: str = LIB_PATH):
     L.chfsi_bfp_bytes.argtypes = [i, i64, vp]
     L.chfsi_bfp_encode.argtypes = [i, vp, i64, vp, vp]
     L.chfsi_bfp_decode.argtypes = [i, vp, i64, vp, vp]
+    L.chfsi_apply_K.argtypes = [vp, vp, vp, vp]
+    L.chfsi_poisson_precond.argtypes = [vp, i, C.c_double, C.c_double, vp, vp, vp]
+    L.chfsi_poisson_solve.argtypes = [vp, vp, vp, vp, vp, vp]
     L.chfsi_last_error.argtypes = [vp]
     L.chfsi_last_error.restype = C.c_char_p
     L.chfsi_destroy.argtypes = [vp]
@@ -294,6 +309,43 @@ class Chfsi:
         self._check(self.L.chfsi_residual(self.ctx, _ptr(HX), _ptr(MX), _ptr(ritz.contiguous()), _ptr(R),
                                           _ptr(res), ld, ld, _stream()))
         return R, res
+
+    # ------------------------------------------------------------ Poisson
+    def _vec(self, x, name):
+        if x.dtype != torch.float64 or x.device.type != "cuda" or not x.is_contiguous() or x.numel() != self.nnodes:
+            raise ValueError(f"{name} must be a contiguous float64 cuda tensor of {self.nnodes} entries")
+
+    def apply_K(self, x, y=None):
+        """y = K x, the Poisson stiffness (chfsi_apply_K)."""
+        self._vec(x, "x")
+        y = torch.empty_like(x) if y is None else y
+        self._vec(y, "y")
+        self._check(self.L.chfsi_apply_K(self.ctx, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def poisson_precond(self, r, degree, lmin, lmax, z=None):
+        """z = P^{-1} r, the Chebyshev-Jacobi preconditioner (chfsi_poisson_precond)."""
+        self._vec(r, "r")
+        z = torch.empty_like(r) if z is None else z
+        self._vec(z, "z")
+        self._check(self.L.chfsi_poisson_precond(self.ctx, int(degree), float(lmin), float(lmax), _ptr(r),
+                                                 _ptr(z), _stream()))
+        return z
+
+    def poisson_solve(self, f, x=None, tol=1e-10, max_iter=5000, cheb_degree=5, lanczos_steps=20,
+                      lambda_max=0.0, range_=20.0):
+        """PCG solve of K x = f - mean(f) (chfsi_poisson_solve); x is the initial
+        guess (zero if None) and is overwritten.  Returns (x, report dict, status)."""
+        self._vec(f, "f")
+        x = torch.zeros_like(f) if x is None else x
+        self._vec(x, "x")
+        o = PcgOpts(float(tol), int(max_iter), int(cheb_degree), int(lanczos_steps), float(lambda_max),
+                    float(range_))
+        rep = PcgReport()
+        rc = self._check(self.L.chfsi_poisson_solve(self.ctx, C.byref(o), _ptr(f), _ptr(x), C.byref(rep),
+                                                    _stream()))
+        out = {k: getattr(rep, k) for k, _ in PcgReport._fields_}
+        return x, out, rc
 
     def mass_diag(self):
         D = torch.empty(self.nnodes, dtype=torch.float64, device=self.device)

@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libchfsi.so")
-SOURCES = ["abi.hip", "hx_kernels.hip", "hx_bf16.hip", "vec_kernels.hip", "dense_kernels.hip", "bfp_kernels.hip"]
+SOURCES = ["abi.hip", "hx_kernels.hip", "hx_bf16.hip", "vec_kernels.hip", "dense_kernels.hip", "bfp_kernels.hip",
+           "poisson.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-munsafe-fp-atomics",

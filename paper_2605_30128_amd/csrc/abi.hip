@@ -211,6 +211,8 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
     L.WP32 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 4);
     L.WPb = take((size_t)m.npairs * m.npad * L.kpad * 2);
     L.delta64 = take((size_t)m.natoms * m.nbeta * m.nbeta * 16);
+    L.poi1d = take((size_t)(m.nq1 * m.n1 + m.nq1 * m.nq1 + m.nq1) * 8);
+    L.KdInv64 = take((size_t)m.M * 8);
     L.persistent_bytes = o;
 
     o = 0;
@@ -232,6 +234,7 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
 // tables of the reference cell (independent host implementation)
 struct HostTables {
     std::vector<double> K, Phi, PhiT, Mref, wq, D;
+    std::vector<double> poi1d, Kdinv;  // Poisson: 1D tables, 1 / diag(K)
 };
 
 void build_tables(const Mesh &m, HostTables &t) {
@@ -276,6 +279,26 @@ void build_tables(const Mesh &m, HostTables &t) {
             t.PhiT[(size_t)I * NP + q] = v;
         }
     }
+    // Poisson 1D tables: l_i(x_q), the collocation derivative on the Gauss
+    // points Dq[a][b] = l'_b(x_a) (Lagrange basis of the Gauss points), and
+    // the 1D Gauss weights
+    t.poi1d.assign((size_t)q1 * n1 + q1 * q1 + q1, 0);
+    for (int a = 0; a < q1; ++a) {
+        for (int i = 0; i < n1; ++i) t.poi1d[a * n1 + i] = l1[a * n1 + i];
+        cardinal(xq, xq[a], l, dl);
+        for (int b = 0; b < q1; ++b) t.poi1d[q1 * n1 + a * q1 + b] = dl[b];
+        t.poi1d[q1 * n1 + q1 * q1 + a] = wqd[a];
+    }
+    // diag(K) of the Poisson stiffness K_IJ = sum_e int grad N_I . grad N_J
+    // (twice the kinetic table's diagonal), summed over the cells of a node
+    std::vector<double> kd((size_t)m.n);
+    for (int I = 0; I < m.n; ++I) {
+        int i = I % n1, j = (I / n1) % n1, k = I / (n1 * n1);
+        kd[I] = detJ * (sx * k1[i * n1 + i] * m1[j * n1 + j] * m1[k * n1 + k] +
+                        sy * m1[i * n1 + i] * k1[j * n1 + j] * m1[k * n1 + k] +
+                        sz * m1[i * n1 + i] * m1[j * n1 + j] * k1[k * n1 + k]);
+    }
+    t.Kdinv.assign(m.M, 0);
     t.D.assign(m.M, 0);
     for (int64_t e = 0; e < m.ncells; ++e) {
         int64_t ex = e % m.ncell[0], ey = (e / m.ncell[0]) % m.ncell[1], ez = e / (m.ncell[0] * m.ncell[1]);
@@ -283,8 +306,10 @@ void build_tables(const Mesh &m, HostTables &t) {
             int i = I % n1, j = (I / n1) % n1, k = I / (n1 * n1);
             int64_t gx = (ex * m.p + i) % m.Nd[0], gy = (ey * m.p + j) % m.Nd[1], gz = (ez * m.p + k) % m.Nd[2];
             t.D[gx + m.Nd[0] * (gy + m.Nd[1] * gz)] += detJ * wg[i] * wg[j] * wg[k];
+            t.Kdinv[gx + m.Nd[0] * (gy + m.Nd[1] * gz)] += kd[I];
         }
     }
+    for (auto &v : t.Kdinv) v = 1.0 / v;
 }
 
 // largest eigenvalue of the symmetric tridiagonal (alpha, beta[1..m-1]) by
@@ -697,6 +722,8 @@ int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B, const 
     if (e == hipSuccess) e = up(L.M64, t.Mref.data(), NP2 * 8);
     if (e == hipSuccess) e = up(L.Wq, t.wq.data(), m.npad * 8);
     if (e == hipSuccess) e = up(L.D64, t.D.data(), m.M * 8);
+    if (e == hipSuccess) e = up(L.poi1d, t.poi1d.data(), t.poi1d.size() * 8);
+    if (e == hipSuccess) e = up(L.KdInv64, t.Kdinv.data(), m.M * 8);
     // colour classes: cells of equal coordinate parity share no node
     std::vector<int> cells;
     cells.reserve(m.ncells);
@@ -1112,6 +1139,185 @@ int chfsi_bfp_encode(int nbits, const float *x, int64_t n, void *out, void *stre
 
 int chfsi_bfp_decode(int nbits, const void *in, int64_t n, float *x, void *stream) {
     return bfp_call(false, nbits, in, n, x, stream);
+}
+
+// ------------------------------------------------------------------ Poisson
+
+static int poisson_check(chfsi_ctx *c) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    if (!kx_supported(c->m.n1, c->m.nq1))
+        return fail(c, CHFSI_E_ARG, "the Poisson operator needs nq1d = degree + 1 or degree + 2");
+    return CHFSI_OK;
+}
+
+static bool overlap(const double *a, const double *b, int64_t n) { return a < b + n && b < a + n; }
+
+// scratch vectors of length M for the Poisson solver (slot k) and the
+// scalar area: partial sums, then the PCG scalars
+static double *poi_vec(chfsi_ctx *c, int k) { return c->S<double>(c->L.Z) + (size_t)k * c->m.M; }
+static double *poi_part(chfsi_ctx *c) { return c->S<double>(c->L.red); }
+static double *poi_sc(chfsi_ctx *c) { return c->S<double>(c->L.red) + kDotPartials; }
+
+static int read_sc(chfsi_ctx *c, hipStream_t s, double *h) {
+    HIPCHK(c, hipMemcpyAsync(h, poi_sc(c), SC_NSC * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return CHFSI_OK;
+}
+
+// z = chi(D^-1 K) D^-1 r by m steps of the Chebyshev iteration for
+// D^-1 K z = D^-1 r from z = 0 on [a, b] (Saad, Iterative Methods for
+// Sparse Linear Systems, Chebyshev acceleration): theta = (a+b)/2,
+// delta = (b-a)/2, sigma = theta/delta, rho_0 = 1/sigma, d_0 = D^-1 r/theta;
+// rho_k = 1/(2 sigma - rho_{k-1}), d_k = rho_k rho_{k-1} d_{k-1}
+// + (2 rho_k/delta) D^-1 (r - K z_k), z_{k+1} = z_k + d_k.  d, Kz: scratch.
+static int cheb_precond(chfsi_ctx *c, int m, double a, double b, const double *r, double *z, double *d, double *Kz,
+                        hipStream_t s) {
+    const int64_t M = c->m.M;
+    const double *dinv = c->P<double>(c->L.KdInv64), *tab = c->P<double>(c->L.poi1d);
+    const double theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    HIPCHK(c, launch_cheb_step(M, true, 0.0, 1.0 / theta, dinv, r, nullptr, d, z, s));
+    for (int k = 1; k < m; ++k) {
+        HIPCHK(c, launch_kx(c, tab, z, Kz, s));
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        HIPCHK(c, launch_cheb_step(M, false, rn * rho, 2.0 * rn / delta, dinv, r, Kz, d, z, s));
+        rho = rn;
+    }
+    return CHFSI_OK;
+}
+
+// Upper bound of the spectrum of D^-1 K: k Lanczos steps on the symmetric
+// D^-1/2 K D^-1/2 from the splitmix64 vector, theta_max + |beta_k|.
+static int poisson_lanczos(chfsi_ctx *c, int steps, double *out, hipStream_t s) {
+    const int64_t M = c->m.M;
+    double *v = poi_vec(c, 0), *vp = poi_vec(c, 1), *w = poi_vec(c, 2), *t = poi_vec(c, 3), *dh = poi_vec(c, 4);
+    double *part = poi_part(c), *sc = poi_sc(c);
+    const double *tab = c->P<double>(c->L.poi1d);
+    double h[SC_NSC];
+    int rc;
+    auto dot = [&](const double *x, const double *y, double &res) -> int {
+        HIPCHK(c, launch_dot2(M, x, y, nullptr, nullptr, part, PCG_SUMS, sc, s));
+        if ((rc = read_sc(c, s, h))) return rc;
+        res = h[SC_SUM0];
+        return CHFSI_OK;
+    };
+    HIPCHK(c, launch_sqrt(M, c->P<double>(c->L.KdInv64), dh, s));
+    HIPCHK(c, launch_splitmix(M, 0, v, s));
+    HIPCHK(c, hipMemsetAsync(vp, 0, M * sizeof(double), s));
+    double nv;
+    if ((rc = dot(v, v, nv))) return rc;
+    HIPCHK(c, launch_axpby_real(M, 0.0, nullptr, 1.0 / std::sqrt(nv), v, nullptr, s));
+    std::vector<double> al, be(1, 0.0);
+    for (int j = 0; j < steps; ++j) {
+        HIPCHK(c, launch_axpby_real(M, 1.0, v, 0.0, t, dh, s));     // t = D^-1/2 v
+        HIPCHK(c, launch_kx(c, tab, t, w, s));                      // w = K t
+        HIPCHK(c, launch_axpby_real(M, 0.0, nullptr, 1.0, w, dh, s));  // w = D^-1/2 w
+        HIPCHK(c, launch_axpby_real(M, -be[j], vp, 1.0, w, nullptr, s));
+        double a;
+        if ((rc = dot(v, w, a))) return rc;
+        al.push_back(a);
+        HIPCHK(c, launch_axpby_real(M, -a, v, 1.0, w, nullptr, s));
+        double b2;
+        if ((rc = dot(w, w, b2))) return rc;
+        const double b = std::sqrt(std::max(b2, 0.0));
+        be.push_back(b);
+        if (b == 0 || !std::isfinite(b)) break;
+        HIPCHK(c, launch_axpby_real(M, 1.0, v, 0.0, vp, nullptr, s));
+        HIPCHK(c, launch_axpby_real(M, 1.0 / b, w, 0.0, v, nullptr, s));
+    }
+    if (!std::isfinite(be.back())) return fail(c, CHFSI_E_NONFINITE, "Lanczos produced a non-finite value");
+    std::vector<double> bt(be.begin(), be.begin() + al.size());
+    *out = tridiag_max(al, bt) + std::fabs(be[al.size()]);
+    return CHFSI_OK;
+}
+
+int chfsi_apply_K(chfsi_ctx *c, const double *x, double *y, void *stream) {
+    int rc = poisson_check(c);
+    if (rc) return rc;
+    if (!x || !y) return fail(c, CHFSI_E_ARG, "x and y must be non-NULL");
+    if (overlap(x, y, c->m.M)) return fail(c, CHFSI_E_ARG, "x and y must not overlap");
+    HIPCHK(c, launch_kx(c, c->P<double>(c->L.poi1d), x, y, S(stream)));
+    return CHFSI_OK;
+}
+
+int chfsi_poisson_precond(chfsi_ctx *c, int degree, double lmin, double lmax, const double *r, double *z,
+                          void *stream) {
+    int rc = poisson_check(c);
+    if (rc) return rc;
+    if (!r || !z) return fail(c, CHFSI_E_ARG, "r and z must be non-NULL");
+    if (overlap(r, z, c->m.M)) return fail(c, CHFSI_E_ARG, "r and z must not overlap");
+    if (degree < 1 || degree > 64) return fail(c, CHFSI_E_ARG, "degree must be in 1..64");
+    if (!(lmin > 0 && lmin < lmax && std::isfinite(lmax))) return fail(c, CHFSI_E_ARG, "need 0 < lmin < lmax finite");
+    return cheb_precond(c, degree, lmin, lmax, r, z, poi_vec(c, 0), poi_vec(c, 1), S(stream));
+}
+
+int chfsi_poisson_solve(chfsi_ctx *c, const chfsi_pcg_opts *o, const double *f, double *x, chfsi_pcg_report *rep,
+                        void *stream) {
+    int rc = poisson_check(c);
+    if (rc) return rc;
+    if (!o || !f || !x) return fail(c, CHFSI_E_ARG, "opts, f and x must be non-NULL");
+    const int64_t M = c->m.M;
+    if (overlap(f, x, M)) return fail(c, CHFSI_E_ARG, "f and x must not overlap");
+    if (!(o->tol > 0) || !std::isfinite(o->tol)) return fail(c, CHFSI_E_ARG, "tol must be positive");
+    if (o->max_iter < 0) return fail(c, CHFSI_E_ARG, "max_iter must be >= 0");
+    if (o->cheb_degree < 1 || o->cheb_degree > 64) return fail(c, CHFSI_E_ARG, "cheb_degree must be in 1..64");
+    if (!(o->lambda_max >= 0) || !std::isfinite(o->lambda_max)) return fail(c, CHFSI_E_ARG, "lambda_max must be >= 0");
+    if (o->lambda_max == 0 && (o->lanczos_steps < 1 || o->lanczos_steps > 1000))
+        return fail(c, CHFSI_E_ARG, "lanczos_steps must be in 1..1000");
+    if (!(o->range > 1) || !std::isfinite(o->range)) return fail(c, CHFSI_E_ARG, "range must be > 1");
+    hipStream_t s = S(stream);
+    using clk = std::chrono::steady_clock;
+    HIPCHK(c, hipStreamSynchronize(s));
+    const auto t0 = clk::now();
+    double lmax = o->lambda_max;
+    if (lmax == 0 && (rc = poisson_lanczos(c, o->lanczos_steps, &lmax, s))) return rc;
+    const double lmin = lmax / o->range;
+    const auto t1 = clk::now();
+    double *r = poi_vec(c, 0), *p = poi_vec(c, 1), *w = poi_vec(c, 2), *z = poi_vec(c, 3), *d = poi_vec(c, 4),
+           *Kz = poi_vec(c, 5);
+    double *part = poi_part(c), *sc = poi_sc(c);
+    const double *tab = c->P<double>(c->L.poi1d);
+    double h[SC_NSC];
+    // r = K x - (f - mean f); z = P^-1 r; delta = r.z, gamma = r.r; p = -z
+    HIPCHK(c, launch_dot2(M, f, nullptr, nullptr, nullptr, part, PCG_SUMS, sc, s));
+    HIPCHK(c, launch_kx(c, tab, x, w, s));
+    HIPCHK(c, launch_pcg_init(M, sc, w, f, r, s));
+    if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s))) return rc;
+    HIPCHK(c, launch_dot2(M, r, z, r, r, part, PCG_FIRST, sc, s));
+    HIPCHK(c, launch_pcg_dir(M, sc, true, z, p, s));
+    if ((rc = read_sc(c, s, h))) return rc;
+    int it = 0;
+    bool conv = std::sqrt(h[SC_GAMMA]) < o->tol;
+    bool bad = !std::isfinite(h[SC_GAMMA]) || !std::isfinite(h[SC_DELTA]);
+    while (!conv && !bad && it < o->max_iter) {
+        HIPCHK(c, launch_kx(c, tab, p, w, s));                                 // w = K p
+        HIPCHK(c, launch_dot2(M, p, w, nullptr, nullptr, part, PCG_ETA, sc, s));  // eta = p.w
+        HIPCHK(c, launch_pcg_update(M, sc, p, w, x, r, s));                    // x += a p, r += a w
+        if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s))) return rc;
+        HIPCHK(c, launch_dot2(M, r, z, r, r, part, PCG_NEXT, sc, s));          // delta, gamma, beta
+        HIPCHK(c, launch_pcg_dir(M, sc, false, z, p, s));                      // p = -z + beta p
+        if ((rc = read_sc(c, s, h))) return rc;
+        ++it;
+        bad = !(h[SC_ETA] > 0) || !std::isfinite(h[SC_ETA]) || !std::isfinite(h[SC_GAMMA]) ||
+              !std::isfinite(h[SC_DELTA]);
+        conv = !bad && std::sqrt(h[SC_GAMMA]) < o->tol;
+    }
+    // zero-mean representative
+    HIPCHK(c, launch_dot2(M, x, nullptr, nullptr, nullptr, part, PCG_SUMS, sc, s));
+    HIPCHK(c, launch_sub_mean(M, sc, x, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const auto t2 = clk::now();
+    if (rep) {
+        rep->iters = it;
+        rep->converged = conv ? 1 : 0;
+        rep->res_norm = std::sqrt(std::max(h[SC_GAMMA], 0.0));
+        rep->lambda_min = lmin;
+        rep->lambda_max = lmax;
+        rep->t_lanczos = std::chrono::duration<double>(t1 - t0).count();
+        rep->t_total = std::chrono::duration<double>(t2 - t0).count();
+    }
+    if (bad) return fail(c, CHFSI_E_NONFINITE, "PCG breakdown: non-finite scalar or non-positive p.Kp");
+    return conv ? CHFSI_OK : CHFSI_NOT_CONVERGED;
 }
 
 const char *chfsi_last_error(const chfsi_ctx *c) {

@@ -45,6 +45,8 @@ struct Layout {
     size_t WPb;                              // bfloat16 [npairs][npad][kpad]: same, k contiguous
     int kpad;                                // 4 nbeta rounded up to 32
     size_t delta64;                          // complex128 [natoms][nbeta][nbeta]
+    size_t poi1d;                            // double: l_i(x_q) [nq1][n1] | Dq [nq1][nq1] | w [nq1]
+    size_t KdInv64;                          // double [M]: 1 / diag(K) of the Poisson stiffness
     size_t persistent_bytes;
     // scratch
     size_t partial, dcoef;                   // complex128 [npairs|natoms][nbeta][max_nvec]
@@ -149,6 +151,27 @@ hipError_t launch_scale_cols(int N, const double *w, const cd *A, cd *B, hipStre
 hipError_t launch_colnorm(int64_t rows, int64_t nvec, int64_t ld, const cd *A, double *red, double *out,
                           hipStream_t s);
 hipError_t launch_diag(int N, const double *scale, cd *T, hipStream_t s);
+// Poisson (FP64): y = K x, PCG and Chebyshev-Jacobi vector kernels
+enum : int { SC_DELTA = 0, SC_ETA = 1, SC_GAMMA = 2, SC_BETA = 3, SC_SUM0 = 4, SC_SUM1 = 5, SC_NSC = 8 };
+enum : int { PCG_SUMS = 0, PCG_ETA = 1, PCG_FIRST = 2, PCG_NEXT = 3 };
+constexpr int kDotPartials = 2 * 512;  // doubles of partial sums used by launch_dot2
+bool kx_supported(int n1, int q1);
+hipError_t launch_kx(const chfsi_ctx *c, const double *tab, const double *x, double *y, hipStream_t s);
+hipError_t launch_dot2(int64_t n, const double *a, const double *b, const double *c, const double *d, double *part,
+                       int op, double *sc, hipStream_t s);
+hipError_t launch_pcg_update(int64_t n, const double *sc, const double *p, const double *w, double *x, double *r,
+                             hipStream_t s);
+hipError_t launch_pcg_dir(int64_t n, const double *sc, bool first, const double *z, double *p, hipStream_t s);
+hipError_t launch_pcg_init(int64_t n, const double *sc, const double *Kx, const double *f, double *r,
+                           hipStream_t s);
+hipError_t launch_sub_mean(int64_t n, const double *sc, double *x, hipStream_t s);
+hipError_t launch_cheb_step(int64_t n, bool first, double c1, double c2, const double *dinv, const double *r,
+                            const double *Kz, double *d, double *z, hipStream_t s);
+hipError_t launch_axpby_real(int64_t n, double alpha, const double *x, double beta, double *y,
+                             const double *scale, hipStream_t s);
+hipError_t launch_splitmix(int64_t n, uint64_t seed, double *v, hipStream_t s);
+hipError_t launch_sqrt(int64_t n, const double *x, double *y, hipStream_t s);
+
 hipError_t launch_jacobi_eig(int N, cd *A, cd *A2, cd *V, cd *V2, double *w, double *red,
                              int max_sweeps, hipStream_t s, int *sweeps_out, cd **Vout);
 

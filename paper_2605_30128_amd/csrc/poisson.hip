@@ -1,0 +1,455 @@
+// Poisson operator, Chebyshev-Jacobi preconditioner and fused PCG vector
+// kernels (paper Sec. III-B1 and the matrix-free CG section with Algorithm
+// pcg_fusion), all FP64.
+//
+// Kx: y = K x with K_IJ = sum_e int_e grad N_I . grad N_J (periodic mesh),
+// sum-factorised on the tensor-product cell.  The nodal values of a cell are
+// interpolated to the Gauss points by three 1D contractions with
+// l_i(x_q) (z, y, x), differentiated along each axis there by the Gauss-point
+// collocation derivative Dq (exact: a degree-p polynomial is reproduced by
+// its interpolant on nq1 >= p+1 points), scaled by w_q |J| (2/h_d)^2,
+// multiplied by Dq^T and taken back to the nodes by the transposed
+// contractions: O(d p^(d+1)) work per cell instead of O(p^(2d)).
+//
+// One wave per cell.  A lane owns one 1D line of the cube in each phase, so
+// the three gradient lines and their transposed derivatives stay in
+// registers (the paper's register/shared-memory hybrid); only the values at
+// the Gauss points and the partial sums pass through two LDS planes.  The
+// gather of the first phase goes straight into registers (one z-line per
+// lane) and the last contraction is assembled from registers with FP64
+// atomic adds, so y is zeroed first.
+#include "cell_common.h"
+
+namespace chfsi {
+
+struct KxParams {
+    const double *x;
+    double *y;
+    int64_t ncx, ncy, ncells, Nx, Ny, Nz;
+    int p;
+    const double *tab;  // N1[q1][n1] | Dq[q1][q1] | w1[q1]
+    double cx, cy, cz;  // |J| (2/h_d)^2
+};
+
+constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+__device__ __forceinline__ int64_t wrap1(int64_t g, int64_t N) { return g >= N ? g - N : g; }
+
+template <int N1, int Q1>
+__global__ __launch_bounds__(64) void kx_kernel(KxParams a) {
+    constexpr int SA = cmax3(Q1 * N1 * N1, Q1 * Q1 * Q1, Q1 * Q1 * N1);
+    __shared__ double A[SA], B[SA];
+    __shared__ double tN[Q1 * N1], tD[Q1 * Q1], tw[Q1];
+    const int lane = threadIdx.x;
+    for (int t = lane; t < Q1 * N1; t += 64) tN[t] = a.tab[t];
+    for (int t = lane; t < Q1 * Q1; t += 64) tD[t] = a.tab[Q1 * N1 + t];
+    if (lane < Q1) tw[lane] = a.tab[Q1 * N1 + Q1 * Q1 + lane];
+    const int64_t e = xcd_remap(blockIdx.x, a.ncells);
+    const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
+    const int64_t NxNy = a.Nx * a.Ny;
+    // z-line of lane (j, i): global offsets of its nodes
+    const int li = lane % N1, lj = lane / N1;
+    const int64_t base = wrap1(ex * a.p + li, a.Nx) + a.Nx * wrap1(ey * a.p + lj, a.Ny);
+    const int64_t gz0 = ez * a.p;
+    __syncthreads();
+
+    // 1: gather the z-line into registers and interpolate along z -> A[qz][j][i]
+    if (lane < N1 * N1) {
+        double xv[N1];
+#pragma unroll
+        for (int k = 0; k < N1; ++k) xv[k] = a.x[base + NxNy * wrap1(gz0 + k, a.Nz)];
+#pragma unroll
+        for (int qz = 0; qz < Q1; ++qz) {
+            double s = 0;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) s += tN[qz * N1 + k] * xv[k];
+            A[(qz * N1 + lj) * N1 + li] = s;
+        }
+    }
+    __syncthreads();
+    // 2: along y, lane (qz, i) -> B[qz][qy][i]
+    if (lane < Q1 * N1) {
+        const int qz = lane / N1, i = lane % N1;
+        double v[N1];
+#pragma unroll
+        for (int j = 0; j < N1; ++j) v[j] = A[(qz * N1 + j) * N1 + i];
+#pragma unroll
+        for (int qy = 0; qy < Q1; ++qy) {
+            double s = 0;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) s += tN[qy * N1 + j] * v[j];
+            B[(qz * Q1 + qy) * N1 + i] = s;
+        }
+    }
+    __syncthreads();
+    // 3: along x, lane (qz, qy): values at the Gauss points -> A[qz][qy][qx];
+    //    the x-gradient line and its transposed derivative stay in registers
+    double ux[Q1];
+    if (lane < Q1 * Q1) {
+        const int qz = lane / Q1, qy = lane % Q1;
+        double v[N1], u[Q1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) v[i] = B[(qz * Q1 + qy) * N1 + i];
+#pragma unroll
+        for (int qx = 0; qx < Q1; ++qx) {
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < N1; ++i) s += tN[qx * N1 + i] * v[i];
+            u[qx] = s;
+            A[(qz * Q1 + qy) * Q1 + qx] = s;
+        }
+        const double wzy = tw[qz] * tw[qy] * a.cx;
+        double g[Q1];
+#pragma unroll
+        for (int t = 0; t < Q1; ++t) {
+            double s = 0;
+#pragma unroll
+            for (int b = 0; b < Q1; ++b) s += tD[t * Q1 + b] * u[b];
+            g[t] = s * wzy * tw[t];
+        }
+#pragma unroll
+        for (int qx = 0; qx < Q1; ++qx) {
+            double s = 0;
+#pragma unroll
+            for (int t = 0; t < Q1; ++t) s += tD[t * Q1 + qx] * g[t];
+            ux[qx] = s;
+        }
+    }
+    __syncthreads();
+    // 4: y-gradient, lane (qz, qx) -> B[qz][qy][qx] = Dq^T (W_y dy u)
+    if (lane < Q1 * Q1) {
+        const int qz = lane / Q1, qx = lane % Q1;
+        double u[Q1], g[Q1];
+#pragma unroll
+        for (int qy = 0; qy < Q1; ++qy) u[qy] = A[(qz * Q1 + qy) * Q1 + qx];
+        const double wzx = tw[qz] * tw[qx] * a.cy;
+#pragma unroll
+        for (int t = 0; t < Q1; ++t) {
+            double s = 0;
+#pragma unroll
+            for (int b = 0; b < Q1; ++b) s += tD[t * Q1 + b] * u[b];
+            g[t] = s * wzx * tw[t];
+        }
+#pragma unroll
+        for (int qy = 0; qy < Q1; ++qy) {
+            double s = 0;
+#pragma unroll
+            for (int t = 0; t < Q1; ++t) s += tD[t * Q1 + qy] * g[t];
+            B[(qz * Q1 + qy) * Q1 + qx] = s;
+        }
+    }
+    __syncthreads();
+    // 5: z-gradient, lane (qy, qx) -> B[qz][qy][qx] += Dq^T (W_z dz u)
+    if (lane < Q1 * Q1) {
+        const int qy = lane / Q1, qx = lane % Q1;
+        double u[Q1], g[Q1];
+#pragma unroll
+        for (int qz = 0; qz < Q1; ++qz) u[qz] = A[(qz * Q1 + qy) * Q1 + qx];
+        const double wyx = tw[qy] * tw[qx] * a.cz;
+#pragma unroll
+        for (int t = 0; t < Q1; ++t) {
+            double s = 0;
+#pragma unroll
+            for (int b = 0; b < Q1; ++b) s += tD[t * Q1 + b] * u[b];
+            g[t] = s * wyx * tw[t];
+        }
+#pragma unroll
+        for (int qz = 0; qz < Q1; ++qz) {
+            double s = 0;
+#pragma unroll
+            for (int t = 0; t < Q1; ++t) s += tD[t * Q1 + qz] * g[t];
+            B[(qz * Q1 + qy) * Q1 + qx] += s;
+        }
+    }
+    __syncthreads();
+    // 6: lane (qz, qy): total line, back along x -> A[qz][qy][i]
+    if (lane < Q1 * Q1) {
+        const int qz = lane / Q1, qy = lane % Q1;
+        double s[Q1];
+#pragma unroll
+        for (int qx = 0; qx < Q1; ++qx) s[qx] = ux[qx] + B[(qz * Q1 + qy) * Q1 + qx];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) {
+            double t = 0;
+#pragma unroll
+            for (int qx = 0; qx < Q1; ++qx) t += tN[qx * N1 + i] * s[qx];
+            A[(qz * Q1 + qy) * N1 + i] = t;
+        }
+    }
+    __syncthreads();
+    // 7: back along y, lane (qz, i) -> B[qz][j][i]
+    if (lane < Q1 * N1) {
+        const int qz = lane / N1, i = lane % N1;
+        double v[Q1];
+#pragma unroll
+        for (int qy = 0; qy < Q1; ++qy) v[qy] = A[(qz * Q1 + qy) * N1 + i];
+#pragma unroll
+        for (int j = 0; j < N1; ++j) {
+            double s = 0;
+#pragma unroll
+            for (int qy = 0; qy < Q1; ++qy) s += tN[qy * N1 + j] * v[qy];
+            B[(qz * N1 + j) * N1 + i] = s;
+        }
+    }
+    __syncthreads();
+    // 8: back along z in registers, assembled with atomic adds
+    if (lane < N1 * N1) {
+        double v[Q1];
+#pragma unroll
+        for (int qz = 0; qz < Q1; ++qz) v[qz] = B[(qz * N1 + lj) * N1 + li];
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            double s = 0;
+#pragma unroll
+            for (int qz = 0; qz < Q1; ++qz) s += tN[qz * N1 + k] * v[qz];
+            atomicAdd(a.y + base + NxNy * wrap1(gz0 + k, a.Nz), s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+// Deterministic two-stage sums: each of kDotBlocks workgroups reduces a
+// grid-stride share (wave shuffles, then the four waves in a fixed order)
+// and writes its partials; one workgroup adds the partials as a fixed tree.
+constexpr int kDotBlocks = 512;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// part[2 b + 0] = sum a.b (b == nullptr: sum a), part[2 b + 1] = sum c.d (c == nullptr: 0)
+__global__ __launch_bounds__(256) void dot2_partial_kernel(int64_t n, const double *a, const double *b,
+                                                          const double *c, const double *d, double *part) {
+    __shared__ double s0[4], s1[4];
+    double u = 0, v = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        u += b ? a[i] * b[i] : a[i];
+        if (c) v += c[i] * d[i];
+    }
+    u = wave_sum(u);
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s0[w] = u;
+        s1[w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+        part[2 * blockIdx.x + 1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    }
+}
+
+// op PCG_SUMS:  sc[SUM0], sc[SUM1] = the two sums
+// op PCG_ETA:   sc[ETA] = sum0
+// op PCG_FIRST: sc[DELTA] = sum0, sc[GAMMA] = sum1 (first iteration)
+// op PCG_NEXT:  sc[BETA] = sum0 / sc[DELTA], sc[DELTA] = sum0, sc[GAMMA] = sum1
+__global__ __launch_bounds__(256) void dot2_finish_kernel(const double *part, int op, double *sc) {
+    __shared__ double s0[256], s1[256];
+    const int t = threadIdx.x;
+    s0[t] = part[2 * t] + part[2 * (t + 256)];
+    s1[t] = part[2 * t + 1] + part[2 * (t + 256) + 1];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            s0[t] += s0[t + h];
+            s1[t] += s1[t + h];
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    const double u = s0[0], v = s1[0];
+    switch (op) {
+    case PCG_SUMS:
+        sc[SC_SUM0] = u;
+        sc[SC_SUM1] = v;
+        break;
+    case PCG_ETA:
+        sc[SC_ETA] = u;
+        break;
+    case PCG_FIRST:
+        sc[SC_DELTA] = u;
+        sc[SC_GAMMA] = v;
+        break;
+    default:
+        sc[SC_BETA] = u / sc[SC_DELTA];
+        sc[SC_DELTA] = u;
+        sc[SC_GAMMA] = v;
+        break;
+    }
+}
+
+// ---------------------------------------------------------------- PCG vectors
+// fused update: alpha = delta / eta, x += alpha p, r += alpha w (one pass)
+__global__ void pcg_update_kernel(int64_t n, const double *sc, const double *p, const double *w, double *x,
+                                  double *r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double alpha = sc[SC_DELTA] / sc[SC_ETA];
+    x[i] += alpha * p[i];
+    r[i] += alpha * w[i];
+}
+
+// p = -z + beta p (first: p = -z)
+__global__ void pcg_dir_kernel(int64_t n, const double *sc, bool first, const double *z, double *p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    p[i] = first ? -z[i] : -z[i] + sc[SC_BETA] * p[i];
+}
+
+// r = K x - (f - mean f), mean f = sc[SUM0] / n
+__global__ void pcg_init_kernel(int64_t n, const double *sc, const double *Kx, const double *f, double *r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    r[i] = Kx[i] - (f[i] - sc[SC_SUM0] / (double)n);
+}
+
+// x -= sc[SUM0] / n (zero-mean representative of the periodic solution)
+__global__ void sub_mean_kernel(int64_t n, const double *sc, double *x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    x[i] -= sc[SC_SUM0] / (double)n;
+}
+
+// Chebyshev step on D^-1 K z = D^-1 r, D = diag(K), from z_0 = 0:
+//   first: d = c2 D^-1 r, z = d
+//   else:  d = c1 d + c2 D^-1 (r - K z), z += d
+__global__ void cheb_step_kernel(int64_t n, bool first, double c1, double c2, const double *dinv, const double *r,
+                                 const double *Kz, double *d, double *z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (first) {
+        const double v = c2 * dinv[i] * r[i];
+        d[i] = v;
+        z[i] = v;
+        return;
+    }
+    const double v = c1 * d[i] + c2 * dinv[i] * (r[i] - Kz[i]);
+    d[i] = v;
+    z[i] += v;
+}
+
+// y = s (alpha x + beta y); x may be null (y = s beta y), s may be null (no scale)
+__global__ void axpby_real_kernel(int64_t n, double alpha, const double *x, double beta, double *y,
+                                  const double *s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = beta * y[i] + (x ? alpha * x[i] : 0.0);
+    y[i] = s ? s[i] * v : v;
+}
+
+// Start vector of the Lanczos run: splitmix64 (Steele, Lea and Flood 2014)
+// of the state seed + (i + 1) 0x9E3779B97F4A7C15, top 53 bits as a uniform
+// double in [-0.5, 0.5).
+__global__ void splitmix_kernel(int64_t n, uint64_t seed, double *v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v[i] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+}
+
+__global__ void sqrt_kernel(int64_t n, const double *x, double *y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = sqrt(x[i]);
+}
+
+static dim3 g1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+template <int N1, int Q1>
+static void kx_go(const KxParams &a, int64_t ncells, hipStream_t s) {
+    hipLaunchKernelGGL((kx_kernel<N1, Q1>), dim3((unsigned)ncells), dim3(64), 0, s, a);
+}
+
+bool kx_supported(int n1, int q1) { return n1 >= 2 && n1 <= 8 && (q1 == n1 || (q1 == n1 + 1 && q1 <= 8)); }
+
+hipError_t launch_kx(const chfsi_ctx *c, const double *tab, const double *x, double *y, hipStream_t s) {
+    const Mesh &m = c->m;
+    if (!kx_supported(m.n1, m.nq1)) return hipErrorInvalidValue;
+    hipError_t e = hipMemsetAsync(y, 0, (size_t)m.M * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    KxParams a{};
+    a.x = x;
+    a.y = y;
+    a.ncx = m.ncell[0];
+    a.ncy = m.ncell[1];
+    a.ncells = m.ncells;
+    a.Nx = m.Nd[0];
+    a.Ny = m.Nd[1];
+    a.Nz = m.Nd[2];
+    a.p = m.p;
+    a.tab = tab;
+    const double detJ = m.h[0] * m.h[1] * m.h[2] / 8.0;
+    a.cx = detJ * 4.0 / (m.h[0] * m.h[0]);
+    a.cy = detJ * 4.0 / (m.h[1] * m.h[1]);
+    a.cz = detJ * 4.0 / (m.h[2] * m.h[2]);
+    switch (m.n1 * 16 + m.nq1) {
+#define KX_CASE(N, Q) \
+    case N * 16 + Q: kx_go<N, Q>(a, m.ncells, s); break;
+        KX_CASE(2, 2) KX_CASE(2, 3) KX_CASE(3, 3) KX_CASE(3, 4) KX_CASE(4, 4) KX_CASE(4, 5) KX_CASE(5, 5)
+        KX_CASE(5, 6) KX_CASE(6, 6) KX_CASE(6, 7) KX_CASE(7, 7) KX_CASE(7, 8) KX_CASE(8, 8)
+#undef KX_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dot2(int64_t n, const double *a, const double *b, const double *c, const double *d, double *part,
+                       int op, double *sc, hipStream_t s) {
+    static_assert(kDotBlocks == 512, "the finish kernel folds 512 partials");
+    hipLaunchKernelGGL(dot2_partial_kernel, dim3(kDotBlocks), dim3(256), 0, s, n, a, b, c, d, part);
+    hipLaunchKernelGGL(dot2_finish_kernel, dim3(1), dim3(256), 0, s, (const double *)part, op, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(int64_t n, const double *sc, const double *p, const double *w, double *x, double *r,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(pcg_update_kernel, g1(n), dim3(256), 0, s, n, sc, p, w, x, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_dir(int64_t n, const double *sc, bool first, const double *z, double *p, hipStream_t s) {
+    hipLaunchKernelGGL(pcg_dir_kernel, g1(n), dim3(256), 0, s, n, sc, first, z, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(int64_t n, const double *sc, const double *Kx, const double *f, double *r,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(pcg_init_kernel, g1(n), dim3(256), 0, s, n, sc, Kx, f, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_mean(int64_t n, const double *sc, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(sub_mean_kernel, g1(n), dim3(256), 0, s, n, sc, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_cheb_step(int64_t n, bool first, double c1, double c2, const double *dinv, const double *r,
+                            const double *Kz, double *d, double *z, hipStream_t s) {
+    hipLaunchKernelGGL(cheb_step_kernel, g1(n), dim3(256), 0, s, n, first, c1, c2, dinv, r, Kz, d, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby_real(int64_t n, double alpha, const double *x, double beta, double *y,
+                             const double *scale, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_real_kernel, g1(n), dim3(256), 0, s, n, alpha, x, beta, y, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_splitmix(int64_t n, uint64_t seed, double *v, hipStream_t s) {
+    hipLaunchKernelGGL(splitmix_kernel, g1(n), dim3(256), 0, s, n, seed, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqrt(int64_t n, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(sqrt_kernel, g1(n), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace chfsi

@@ -94,6 +94,9 @@ def test_null_context_calls_fail_cleanly(lib):
     assert L.chfsi_apply_H(None, 0, None, None, 1, 1, None) == binding.E_ARG
     assert L.chfsi_filter(None, 0, 5, None, None, None, None, None, 1, 1, None) == binding.E_ARG
     assert L.chfsi_solve(None, 1, None, None, 2, 2, None, None, None, None, None, 0, None) == binding.E_ARG
+    assert L.chfsi_apply_K(None, None, None, None) == binding.E_ARG
+    assert L.chfsi_poisson_precond(None, 5, 0.1, 2.0, None, None, None) == binding.E_ARG
+    assert L.chfsi_poisson_solve(None, None, None, None, None, None) == binding.E_ARG
     L.chfsi_destroy(None)
 
 
