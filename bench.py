@@ -91,6 +91,123 @@ def bfp_throughput(n=1 << 28, reps=5):
     return out
 
 
+def kx_flops(degree, nq1, ncells):
+    """Algorithmic flops of one sum-factorised K x (Sec. III-B1): per cell
+    three interpolations to the Gauss points (n^3 q + n^2 q^2 + n q^3 FMAs),
+    the three gradients and their transposes (6 q^4) and the three
+    transposed interpolations (as many as the first three), 2 flops per FMA."""
+    n, q = degree + 1, nq1
+    return ncells * 2 * (2 * (n ** 3 * q + n ** 2 * q ** 2 + n * q ** 3) + 6 * q ** 4)
+
+
+def poisson_leg(reps=50, pcg_solve=True):
+    """The Poisson workload of the paper's electrostatics (Sec. III-B1): the
+    matrix-free K x throughput (DoF/s) and its roofline on the medium mesh
+    (p = 6) and on the largest one-GPU shape at p = 7 (the degree of the
+    paper's K x comparison), and the PCG solve with a degree-5
+    Chebyshev-Jacobi preconditioner to the absolute residual 1e-10 for a
+    neutral Gaussian charge (f = 4 pi D rho, D the GLL-lumped mass)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2605_30128_amd import binding, synth
+    out = {}
+    for name in ("medium", "slab"):
+        c = synth.CONFIGS[name]
+        prob = synth.make_problem(ncell=c["ncell"], box=c["box"], degree=c["degree"], nwells=1, natoms=0,
+                                  bfield="zero", soc=False, seed=c["seed"])
+        ctx = binding.Chfsi(prob, max_nvec=1)
+        M = ctx.nnodes
+        g = torch.Generator(device="cuda").manual_seed(5)
+        x = torch.randn(M, generator=g, device="cuda", dtype=torch.float64)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            ctx.apply_K(x, y)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            ctx.apply_K(x, y)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+        fl = kx_flops(prob.degree, prob.nq1, prob.ncells)
+        rec = {"nodes": M, "cells": prob.ncells, "degree": prob.degree, "us_per_apply": t * 1e6,
+               "gdof_per_s": M / t / 1e9,
+               "roofline": {"bound": "alu", "achieved": fl / t / 1e12, "peak": PEAK["fp64"] / 1e12,
+                            "unit": "TFLOP/s", "frac": fl / t / PEAK["fp64"], "traffic": kx_traffic(name),
+                            "kernel": "apply_K: zero fill of y + kx_kernel (one launch)",
+                            "flops_per_launch": fl, "hbm_GBps_16B_per_node": 16 * M / t / 1e9}}
+        X = synth.node_coords(prob.ncell, prob.h, prob.degree)
+        rho = synth.neutral_charge(X, prob.box, ncentres=8, seed=c["seed"])
+        del X
+        D = ctx.mass_diag()
+        f = 4 * math.pi * D * torch.from_numpy(rho).cuda()
+        del rho
+        pcg = {}
+        for deg in ((1, 5) if pcg_solve else ()):
+            xs, rep, rc = ctx.poisson_solve(f, tol=1e-10, max_iter=20000, cheb_degree=deg, lanczos_steps=20)
+            r = ctx.apply_K(xs) - (f - f.mean())
+            pcg[f"cheb{deg}"] = {"status": rc, "iters": rep["iters"], "t_solve_s": rep["t_total"],
+                                 "t_lanczos_s": rep["t_lanczos"],
+                                 "ms_per_iter": 1e3 * (rep["t_total"] - rep["t_lanczos"]) / max(rep["iters"], 1),
+                                 "res_norm": rep["res_norm"], "true_res_norm": float(r.norm()),
+                                 "lambda_max": rep["lambda_max"]}
+        rec["pcg_tol_abs_1e-10"] = pcg
+        out[name] = rec
+        log(f"[bench] poisson {name}: K x {t * 1e6:.1f} us ({M / t / 1e9:.1f} GDoF/s, "
+            f"{fl / t / 1e12:.1f} TFLOP/s); PCG " +
+            ", ".join(f"{k}: {v['iters']} it {v['t_solve_s'] * 1e3:.1f} ms" for k, v in pcg.items()))
+        del ctx, x, y, f
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_poisson_baseline(name="medium"):
+    """The oracle's K x (quadrature definition, numpy) on the medium mesh."""
+    import numpy as np
+
+    import oracle
+    from oracle import poisson
+    from paper_2605_30128_amd import synth
+    oracle.build(force=False)
+    c = synth.CONFIGS[name]
+    prob = synth.make_problem(ncell=c["ncell"], box=c["box"], degree=c["degree"], nwells=1, natoms=0,
+                              bfield="zero", soc=False, seed=c["seed"])
+    K = poisson.Stiffness(oracle.Oracle(prob))
+    x = np.random.default_rng(1).standard_normal(K.M)
+    K.apply(x)
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        K.apply(x)
+    dt = (time.perf_counter() - t0) / reps
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": K.M / dt / 1e9, "unit": "GDoF/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} K x on the {name} mesh ({K.M} nodes), {dt:.3f} s each"}
+
+
+def kx_traffic(config):
+    """HBM bytes per K x launch from the committed counter summary (calibrated
+    FETCH_SIZE + WRITE_SIZE), or None if the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "kx_kernel_medium_slab_counters.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+            if rec.get("config") != config:
+                continue
+            with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                    return None
+            return 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_scale"] +
+                             rec["write_kib_per_launch"] * rec["write_scale"])
+    return None
+
+
 def measured_traffic(prec, config, nvec):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, calibrated), or None when the
@@ -186,6 +303,12 @@ def main():
                     help="only the H X products (for counter runs), after a 1 GiB fill and a 1 GiB sum that "
                          "calibrate the memory counters")
     ap.add_argument("--hx-precs", default="fp64,fp32,bf16")
+    ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson (K x, PCG) leg")
+    ap.add_argument("--poisson-only", action="store_true", help="run only the Poisson leg")
+    ap.add_argument("--no-pcg", action="store_true", help="Poisson leg: K x only")
+    ap.add_argument("--kx-reps", type=int, default=50)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="with --poisson-only: run the 1 GiB fill and sum used to scale memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
@@ -200,6 +323,19 @@ def main():
     binding.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.poisson_only:
+        if args.calibrate:
+            # memory-counter calibration: a fill writes 2^30 bytes, a sum reads them
+            a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+            a.fill_(1.0)
+            a.sum().item()
+            torch.cuda.synchronize()
+            del a
+        poi = poisson_leg(reps=args.kx_reps, pcg_solve=not args.no_pcg)
+        if not args.no_cpu_baseline:
+            poi["cpu_baseline"] = cpu_poisson_baseline()
+        print(json.dumps({"poisson": poi}), flush=True)
+        return
     cfg = synth.CONFIGS[args.config]
     t0 = time.perf_counter()
     p = synth.make_config(args.config)
@@ -299,6 +435,15 @@ def main():
     log(f"[bench] bfp codec: " + ", ".join(f"{k} enc {v['encode_GBps']:.0f} / dec {v['decode_GBps']:.0f} GB/s"
                                            for k, v in bfp.items()))
 
+    poi = None
+    if not args.no_poisson:
+        poi = poisson_leg()
+        if not args.no_cpu_baseline:
+            try:
+                poi["cpu_baseline"] = cpu_poisson_baseline()
+            except Exception as e:  # the baseline is a report, never the product
+                log(f"[bench] cpu poisson baseline failed: {e}")
+
     cpu = None
     if not args.no_cpu_baseline:
         try:
@@ -334,6 +479,7 @@ def main():
         "hx_profile_ms": prof,
         "roofline": roof,
         "bfp_codec": bfp,
+        "poisson": poi,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -209,7 +209,7 @@ typedef struct {
                            factor of Y^H M Y (chfsi_rayleigh_ritz_general),
                            falling back to mode 0 on a Cholesky breakdown;
                            2: as 1 with the paper's mixed-precision subspace
-                           rotation (Sec. III-C5, RR-SR): X <- Y Q with the
+                           rotation (Sec. III-C4, RR-SR): X <- Y Q with the
                            diagonal 64 x 64 blocks of Q in FP64 and the rest
                            in FP32 (complex64 copies, FP32 MFMA), summed in
                            FP64; the residual products stay FP64.
@@ -262,7 +262,7 @@ int chfsi_info(const chfsi_ctx *ctx, int64_t *nnodes, int64_t *ncells, int *n, i
 /* The diagonal D (GLL-integrated mass, Sec. III-B2) as double device [M]. */
 int chfsi_mass_diag(chfsi_ctx *ctx, double *D, void *stream);
 
-/* Block floating-point codec (Sec. III-C4, compressed communication, fig.
+/* Block floating-point codec (Sec. III-C3, compressed communication, fig.
  * layout).  Four float values form one block of N_bits = 4*nbits bits,
  * nbits in {16, 12, 10}: the low 8 bits hold the shared biased exponent
  * e = e_max + 127 with 2^(e_max-1) <= max|x_i| < 2^e_max (e_max >= -126; 0
@@ -287,8 +287,8 @@ int chfsi_bfp_decode(int nbits, const void *in, int64_t n, float *x, void *strea
  * III-B1): K_IJ = sum_e int_e grad N_I . grad N_J on the context's periodic
  * mesh, with the same nodes and Gauss quadrature as H.  Vectors are double
  * device arrays [M], node index gx + Nx (gy + Ny gz), owned by the caller.
- * K is assembled matrix-free and sum-factorised (Sec. III-B1, the Kx kernel
- * paragraph: extraction, 1D contractions, Jacobian and assembly in one
+ * K is assembled matrix-free and sum-factorised (Sec. III-B1; Sec. III-C1, the
+ * K x kernel paragraph: extraction, 1D contractions, Jacobian and assembly in one
  * launch); it needs nq1d = degree + 1 or degree + 2 (else CHFSI_E_ARG).  K
  * is symmetric positive semi-definite; its null space is the constants. */
 
@@ -296,7 +296,7 @@ int chfsi_bfp_decode(int nbits, const void *in, int64_t n, float *x, void *strea
  * atomic adds, so the last bits of y may differ between calls). */
 int chfsi_apply_K(chfsi_ctx *ctx, const double *x, double *y, void *stream);
 
-/* Chebyshev-Jacobi preconditioner of the PCG section: z = P^{-1} r with
+/* Chebyshev-Jacobi preconditioner (Sec. III-B1; Sec. III-C1): z = P^{-1} r with
  * P^{-1} = chi(D^{-1} K) D^{-1}, D = diag(K), chi the degree-m Chebyshev
  * approximation of 1/lambda on [lmin, lmax] (m steps of the Chebyshev
  * iteration on D^{-1} K z = D^{-1} r from z = 0, m - 1 applications of K;
@@ -323,7 +323,7 @@ typedef struct {
 } chfsi_pcg_report;
 
 /* Solves K x = f' with f' = f - mean(f) (the part of f in the range of K) by
- * the PCG of Algorithm pcg_fusion: w = K p; eta = p.w; alpha = delta/eta;
+ * the PCG of Algorithm pcg_fusion (Sec. III-C1): w = K p; eta = p.w; alpha = delta/eta;
  * x += alpha p and r += alpha w in one pass; z = P^{-1} r; (delta_new,
  * gamma) = (r.z, r.r) in one reduction; beta = delta_new/delta; p = -z +
  * beta p; stop when sqrt(gamma) < tol.  r = K x - f' starts from the

@@ -5,7 +5,7 @@ import this module; the product path never does.  It shares no code with the
 GPU library.
 
 Written from the paper's description of its lightweight BFP compression
-(Sec. III-C4, the compressed-communication paragraphs and fig. layout):
+(Sec. III-C3, the compressed-communication paragraphs and fig. layout):
 
 * four FP32 values form a block of N_bits = 4 n_bits bits; the low 8 bits
   hold a shared biased exponent, the remaining N_bits - 8 bits four signed

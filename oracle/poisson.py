@@ -11,14 +11,14 @@ pinned by the basis tests), everything else is written here from the paper.
   every Gauss point G_e = dN x_e, then K_e x_e = G^T (w |J|) G x_e -- and
   assembled by summing into the global nodes.  No sum factorisation.
 * diag(K): the same quadrature of |grad N_I|^2, summed over the cells of I.
-* Chebyshev-Jacobi preconditioner (PCG section, preconditioner paragraph):
+* Chebyshev-Jacobi preconditioner (Sec. III-B1; Sec. III-C1, preconditioner paragraph):
   P^{-1} = chi(D^{-1} K) D^{-1}, D = diag(K), chi of degree m approximating
   1/lambda on [lmin, lmax], applied as m steps of the Chebyshev iteration for
   D^{-1} K z = D^{-1} r from z = 0 (Saad, Iterative Methods for Sparse
   Linear Systems, Chebyshev acceleration).
 * Spectral bound: Lanczos on D^{-1/2} K D^{-1/2}, theta_max + |beta_k|, from
   the splitmix64 start vector (Steele, Lea and Flood 2014).
-* PCG: Algorithm pcg_fusion in its order (w = K p, eta, alpha, the x and r
+* PCG: Algorithm pcg_fusion (Sec. III-C1) in its order (w = K p, eta, alpha, the x and r
   update, z = P^{-1} r, delta_new and gamma, beta, the new p, the test
   sqrt(gamma) < tol), on f' = f - mean(f), returning the zero-mean solution.
 

@@ -211,7 +211,6 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
     L.WP32 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 4);
     L.WPb = take((size_t)m.npairs * m.npad * L.kpad * 2);
     L.delta64 = take((size_t)m.natoms * m.nbeta * m.nbeta * 16);
-    L.poi1d = take((size_t)(m.nq1 * m.n1 + m.nq1 * m.nq1 + m.nq1) * 8);
     L.KdInv64 = take((size_t)m.M * 8);
     L.persistent_bytes = o;
 
@@ -279,15 +278,31 @@ void build_tables(const Mesh &m, HostTables &t) {
             t.PhiT[(size_t)I * NP + q] = v;
         }
     }
-    // Poisson 1D tables: l_i(x_q), the collocation derivative on the Gauss
-    // points Dq[a][b] = l'_b(x_a) (Lagrange basis of the Gauss points), and
-    // the 1D Gauss weights
-    t.poi1d.assign((size_t)q1 * n1 + q1 * q1 + q1, 0);
-    for (int a = 0; a < q1; ++a) {
-        for (int i = 0; i < n1; ++i) t.poi1d[a * n1 + i] = l1[a * n1 + i];
-        cardinal(xq, xq[a], l, dl);
-        for (int b = 0; b < q1; ++b) t.poi1d[q1 * n1 + a * q1 + b] = dl[b];
-        t.poi1d[q1 * n1 + q1 * q1 + a] = wqd[a];
+    // Poisson 1D operators in the even/odd form of the K x kernel: for each
+    // of N[q][i] = l_i(x_q), N^T, Dq[a][b] = l'_b(x_a) (collocation
+    // derivative: Lagrange basis of the Gauss points) and Dq^T, the first
+    // ceil(rows/2) rows of E = (T[a][b] + T[a][ni-1-b]) / 2 (middle column
+    // as is) and O = (T[a][b] - T[a][ni-1-b]) / 2; then the Gauss weights.
+    {
+        std::vector<double> N((size_t)q1 * n1), NT((size_t)n1 * q1), Dq((size_t)q1 * q1), DT((size_t)q1 * q1);
+        for (int a = 0; a < q1; ++a) {
+            for (int i = 0; i < n1; ++i) N[a * n1 + i] = NT[i * q1 + a] = l1[a * n1 + i];
+            cardinal(xq, xq[a], l, dl);
+            for (int b = 0; b < q1; ++b) Dq[a * q1 + b] = DT[b * q1 + a] = dl[b];
+        }
+        t.poi1d.clear();
+        auto eo = [&](const std::vector<double> &T, int no, int ni) {
+            for (int a = 0; a < (no + 1) / 2; ++a)
+                for (int b = 0; b < (ni + 1) / 2; ++b)
+                    t.poi1d.push_back(2 * b + 1 == ni ? T[a * ni + b] : 0.5 * (T[a * ni + b] + T[a * ni + ni - 1 - b]));
+            for (int a = 0; a < (no + 1) / 2; ++a)
+                for (int b = 0; b < ni / 2; ++b) t.poi1d.push_back(0.5 * (T[a * ni + b] - T[a * ni + ni - 1 - b]));
+        };
+        eo(N, q1, n1);
+        eo(NT, n1, q1);
+        eo(Dq, q1, q1);
+        eo(DT, q1, q1);
+        for (int a = 0; a < q1; ++a) t.poi1d.push_back(wqd[a]);
     }
     // diag(K) of the Poisson stiffness K_IJ = sum_e int grad N_I . grad N_J
     // (twice the kinetic table's diagonal), summed over the cells of a node
@@ -476,7 +491,7 @@ int rotate(chfsi_ctx *c, cd *A, const cd *Q, int64_t N, int64_t ld, hipStream_t 
 }
 
 // A <- A Q with the paper's mixed-precision subspace rotation (RR-SR, Sec.
-// III-C5 on the Rayleigh-Ritz step): the diagonal SRB x SRB blocks of Q in
+// III-C4, the Rayleigh-Ritz step): the diagonal SRB x SRB blocks of Q in
 // FP64 (one strided-batched zgemm), the off-diagonal part in FP32 (cgemm on
 // complex64 copies of A and of Q with its diagonal blocks zeroed), summed in
 // FP64.  Q32 is scratch for an N x N complex64 matrix.
@@ -722,7 +737,7 @@ int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B, const 
     if (e == hipSuccess) e = up(L.M64, t.Mref.data(), NP2 * 8);
     if (e == hipSuccess) e = up(L.Wq, t.wq.data(), m.npad * 8);
     if (e == hipSuccess) e = up(L.D64, t.D.data(), m.M * 8);
-    if (e == hipSuccess) e = up(L.poi1d, t.poi1d.data(), t.poi1d.size() * 8);
+    for (size_t i = 0; i < t.poi1d.size() && i < (size_t)kPoiTab; ++i) c->poi_tab[i] = t.poi1d[i];
     if (e == hipSuccess) e = up(L.KdInv64, t.Kdinv.data(), m.M * 8);
     // colour classes: cells of equal coordinate parity share no node
     std::vector<int> cells;
@@ -1173,12 +1188,12 @@ static int read_sc(chfsi_ctx *c, hipStream_t s, double *h) {
 static int cheb_precond(chfsi_ctx *c, int m, double a, double b, const double *r, double *z, double *d, double *Kz,
                         hipStream_t s) {
     const int64_t M = c->m.M;
-    const double *dinv = c->P<double>(c->L.KdInv64), *tab = c->P<double>(c->L.poi1d);
+    const double *dinv = c->P<double>(c->L.KdInv64);
     const double theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
     double rho = 1.0 / sigma;
     HIPCHK(c, launch_cheb_step(M, true, 0.0, 1.0 / theta, dinv, r, nullptr, d, z, s));
     for (int k = 1; k < m; ++k) {
-        HIPCHK(c, launch_kx(c, tab, z, Kz, s));
+        HIPCHK(c, launch_kx(c, z, Kz, s));
         const double rn = 1.0 / (2.0 * sigma - rho);
         HIPCHK(c, launch_cheb_step(M, false, rn * rho, 2.0 * rn / delta, dinv, r, Kz, d, z, s));
         rho = rn;
@@ -1192,7 +1207,6 @@ static int poisson_lanczos(chfsi_ctx *c, int steps, double *out, hipStream_t s) 
     const int64_t M = c->m.M;
     double *v = poi_vec(c, 0), *vp = poi_vec(c, 1), *w = poi_vec(c, 2), *t = poi_vec(c, 3), *dh = poi_vec(c, 4);
     double *part = poi_part(c), *sc = poi_sc(c);
-    const double *tab = c->P<double>(c->L.poi1d);
     double h[SC_NSC];
     int rc;
     auto dot = [&](const double *x, const double *y, double &res) -> int {
@@ -1210,7 +1224,7 @@ static int poisson_lanczos(chfsi_ctx *c, int steps, double *out, hipStream_t s) 
     std::vector<double> al, be(1, 0.0);
     for (int j = 0; j < steps; ++j) {
         HIPCHK(c, launch_axpby_real(M, 1.0, v, 0.0, t, dh, s));     // t = D^-1/2 v
-        HIPCHK(c, launch_kx(c, tab, t, w, s));                      // w = K t
+        HIPCHK(c, launch_kx(c, t, w, s));                      // w = K t
         HIPCHK(c, launch_axpby_real(M, 0.0, nullptr, 1.0, w, dh, s));  // w = D^-1/2 w
         HIPCHK(c, launch_axpby_real(M, -be[j], vp, 1.0, w, nullptr, s));
         double a;
@@ -1236,7 +1250,7 @@ int chfsi_apply_K(chfsi_ctx *c, const double *x, double *y, void *stream) {
     if (rc) return rc;
     if (!x || !y) return fail(c, CHFSI_E_ARG, "x and y must be non-NULL");
     if (overlap(x, y, c->m.M)) return fail(c, CHFSI_E_ARG, "x and y must not overlap");
-    HIPCHK(c, launch_kx(c, c->P<double>(c->L.poi1d), x, y, S(stream)));
+    HIPCHK(c, launch_kx(c, x, y, S(stream)));
     return CHFSI_OK;
 }
 
@@ -1276,11 +1290,10 @@ int chfsi_poisson_solve(chfsi_ctx *c, const chfsi_pcg_opts *o, const double *f, 
     double *r = poi_vec(c, 0), *p = poi_vec(c, 1), *w = poi_vec(c, 2), *z = poi_vec(c, 3), *d = poi_vec(c, 4),
            *Kz = poi_vec(c, 5);
     double *part = poi_part(c), *sc = poi_sc(c);
-    const double *tab = c->P<double>(c->L.poi1d);
     double h[SC_NSC];
     // r = K x - (f - mean f); z = P^-1 r; delta = r.z, gamma = r.r; p = -z
     HIPCHK(c, launch_dot2(M, f, nullptr, nullptr, nullptr, part, PCG_SUMS, sc, s));
-    HIPCHK(c, launch_kx(c, tab, x, w, s));
+    HIPCHK(c, launch_kx(c, x, w, s));
     HIPCHK(c, launch_pcg_init(M, sc, w, f, r, s));
     if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s))) return rc;
     HIPCHK(c, launch_dot2(M, r, z, r, r, part, PCG_FIRST, sc, s));
@@ -1290,7 +1303,7 @@ int chfsi_poisson_solve(chfsi_ctx *c, const chfsi_pcg_opts *o, const double *f, 
     bool conv = std::sqrt(h[SC_GAMMA]) < o->tol;
     bool bad = !std::isfinite(h[SC_GAMMA]) || !std::isfinite(h[SC_DELTA]);
     while (!conv && !bad && it < o->max_iter) {
-        HIPCHK(c, launch_kx(c, tab, p, w, s));                                 // w = K p
+        HIPCHK(c, launch_kx(c, p, w, s));                                 // w = K p
         HIPCHK(c, launch_dot2(M, p, w, nullptr, nullptr, part, PCG_ETA, sc, s));  // eta = p.w
         HIPCHK(c, launch_pcg_update(M, sc, p, w, x, r, s));                    // x += a p, r += a w
         if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s))) return rc;

@@ -1,4 +1,4 @@
-// Block floating-point codec (paper Sec. III-C4, compressed communication,
+// Block floating-point codec (paper Sec. III-C3, compressed communication,
 // fig. layout): four FP32 values share an 8-bit biased exponent stored in
 // the low bits of an N_bits = 4 n_bits block, followed by four signed
 // v_bits = n_bits - 2 coefficients (q_0 lowest), rounded to nearest (ties

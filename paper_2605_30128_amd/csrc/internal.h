@@ -17,6 +17,7 @@ constexpr int kCellThreads = 256;   // threads per workgroup of the FP64/FP32 ce
 constexpr int kMaxN = 512;          // nodes per cell (p <= 7)
 constexpr int kMaxBeta = 16;
 constexpr int kMaxDegree = 256;     // Chebyshev degree limit (Lambda_k table)
+constexpr int kPoiTab = 8 * 8 + 8 * 8 + 8;  // doubles of the Poisson 1D tables (nq1, n1 <= 8)
 
 // complex helpers ------------------------------------------------------------
 struct cd { double x, y; };
@@ -45,7 +46,6 @@ struct Layout {
     size_t WPb;                              // bfloat16 [npairs][npad][kpad]: same, k contiguous
     int kpad;                                // 4 nbeta rounded up to 32
     size_t delta64;                          // complex128 [natoms][nbeta][nbeta]
-    size_t poi1d;                            // double: l_i(x_q) [nq1][n1] | Dq [nq1][nq1] | w [nq1]
     size_t KdInv64;                          // double [M]: 1 / diag(K) of the Poisson stiffness
     size_t persistent_bytes;
     // scratch
@@ -78,6 +78,7 @@ struct chfsi_ctx {
     char *scr;
     int64_t colour_ptr[9];
     rocblas_handle blas;
+    double poi_tab[chfsi::kPoiTab];  // host copy of the Poisson 1D tables (kernel arguments)
     std::string err;
     // typed views
     template <typename T> T *P(size_t off) const { return reinterpret_cast<T *>(pers + off); }
@@ -156,7 +157,7 @@ enum : int { SC_DELTA = 0, SC_ETA = 1, SC_GAMMA = 2, SC_BETA = 3, SC_SUM0 = 4, S
 enum : int { PCG_SUMS = 0, PCG_ETA = 1, PCG_FIRST = 2, PCG_NEXT = 3 };
 constexpr int kDotPartials = 2 * 512;  // doubles of partial sums used by launch_dot2
 bool kx_supported(int n1, int q1);
-hipError_t launch_kx(const chfsi_ctx *c, const double *tab, const double *x, double *y, hipStream_t s);
+hipError_t launch_kx(const chfsi_ctx *c, const double *x, double *y, hipStream_t s);
 hipError_t launch_dot2(int64_t n, const double *a, const double *b, const double *c, const double *d, double *part,
                        int op, double *sc, hipStream_t s);
 hipError_t launch_pcg_update(int64_t n, const double *sc, const double *p, const double *w, double *x, double *r,

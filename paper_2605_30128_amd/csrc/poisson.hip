@@ -1,6 +1,6 @@
 // Poisson operator, Chebyshev-Jacobi preconditioner and fused PCG vector
-// kernels (paper Sec. III-B1 and the matrix-free CG section with Algorithm
-// pcg_fusion), all FP64.
+// kernels (paper Sec. III-B1 and Sec. III-C1, the GPU matrix-free CG solver
+// with Algorithm pcg_fusion), all FP64.
 //
 // Kx: y = K x with K_IJ = sum_e int_e grad N_I . grad N_J (periodic mesh),
 // sum-factorised on the tensor-product cell.  The nodal values of a cell are
@@ -27,23 +27,113 @@ struct KxParams {
     double *y;
     int64_t ncx, ncy, ncells, Nx, Ny, Nz;
     int p;
-    const double *tab;  // N1[q1][n1] | Dq[q1][q1] | w1[q1]
-    double cx, cy, cz;  // |J| (2/h_d)^2
+    double cx, cy, cz;        // |J| (2/h_d)^2
+    double tab[kPoiTab];      // even/odd 1D operators and Gauss weights (KxTab layout)
 };
 
 constexpr int cmax3(int a, int b, int c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
 
 __device__ __forceinline__ int64_t wrap1(int64_t g, int64_t N) { return g >= N ? g - N : g; }
 
+// Even/odd application of a 1D operator T (NO x NI) whose entries satisfy
+// T[NO-1-a][NI-1-b] = S T[a][b] (S = +1 for the interpolation l_i(x_q) and
+// its transpose, -1 for the collocation derivative and its transpose: the
+// GLL nodes and Gauss points are symmetric about the cell midpoint).  With
+// pe_b = v_b + v_{NI-1-b}, me_b = v_b - v_{NI-1-b} (b < NI/2, pe of the
+// middle entry = v_mid) and the tables E = (T[a][b] + T[a][NI-1-b]) / 2,
+// O = (T[a][b] - T[a][NI-1-b]) / 2 over the first ceil(NO/2) rows,
+// e_a = E pe, o_a = O me give out[a] = e_a + o_a and
+// out[NO-1-a] = S (e_a - o_a): half the multiplications of T v.
+template <int NI, int NO, int S>
+__device__ __forceinline__ void eo_apply(const double *E, const double *O, const double (&v)[NI], double (&out)[NO]) {
+    constexpr int HI = NI / 2, HIC = (NI + 1) / 2, HO = (NO + 1) / 2;
+    double pe[HIC], me[HI > 0 ? HI : 1];
+#pragma unroll
+    for (int b = 0; b < HI; ++b) {
+        pe[b] = v[b] + v[NI - 1 - b];
+        me[b] = v[b] - v[NI - 1 - b];
+    }
+    if constexpr (NI & 1) pe[HI] = v[HI];
+#pragma unroll
+    for (int a = 0; a < HO; ++a) {
+        double e = 0, o = 0;
+#pragma unroll
+        for (int b = 0; b < HIC; ++b) e += E[a * HIC + b] * pe[b];
+#pragma unroll
+        for (int b = 0; b < HI; ++b) o += O[a * HI + b] * me[b];
+        out[a] = e + o;
+        if (NO - 1 - a != a) out[NO - 1 - a] = S > 0 ? e - o : o - e;
+    }
+}
+
+// offsets of the even/odd tables in KxParams::tab (built by the host in the
+// same order): interpolation N (Q1 x N1), its transpose (N1 x Q1), the
+// derivative Dq (Q1 x Q1), its transpose, then the 1D Gauss weights
 template <int N1, int Q1>
-__global__ __launch_bounds__(64) void kx_kernel(KxParams a) {
-    constexpr int SA = cmax3(Q1 * N1 * N1, Q1 * Q1 * Q1, Q1 * Q1 * N1);
-    __shared__ double A[SA], B[SA];
-    __shared__ double tN[Q1 * N1], tD[Q1 * Q1], tw[Q1];
+struct KxTab {
+    static constexpr int sz(int no, int ni) { return (no + 1) / 2 * ni; }  // E and O together
+    static constexpr int NE = 0, NO = NE + (Q1 + 1) / 2 * ((N1 + 1) / 2);
+    static constexpr int TE = NE + sz(Q1, N1), TO = TE + (N1 + 1) / 2 * ((Q1 + 1) / 2);
+    static constexpr int DE = TE + sz(N1, Q1), DO = DE + (Q1 + 1) / 2 * ((Q1 + 1) / 2);
+    static constexpr int XE = DE + sz(Q1, Q1), XO = XE + (Q1 + 1) / 2 * ((Q1 + 1) / 2);
+    static constexpr int W = XE + sz(Q1, Q1);
+    static constexpr int total = W + Q1;
+};
+
+// w[idx] for a lane-dependent idx without indexing the kernel-argument
+// table dynamically (which would force a private copy of it)
+template <int Q>
+__device__ __forceinline__ double pick(const double *w, int idx) {
+    double r = 0;
+#pragma unroll
+    for (int t = 0; t < Q; ++t) r = t == idx ? w[t] : r;
+    return r;
+}
+
+// LDS layout of the kernel's six intermediate cubes: plane (qz) stride P
+// and row stride R in doubles, for X[qz][row][col] at qz P + row R + col.
+// A1 = z-interpolated nodes [qz][j][i], B2 = [qz][qy][i], A3 (and B4) =
+// Gauss-point values [qz][qy][qx], A6 = [qz][qy][i], B7 = [qz][j][i].  The
+// strides are chosen so that the 64-bit accesses of each phase (lanes
+// running over two of the three indices) spread over the 64 LDS banks:
+// at most two lanes of a 32-lane pass share a bank (the unpadded cubes
+// have up to eight).
+template <int N1, int Q1> struct KxLds;
+#define KX_LDS(N, Q, PA1, RA1, PB2, RB2, PA3, RA3, PA6, RA6, PB7, RB7)                                          \
+    template <> struct KxLds<N, Q> {                                                                            \
+        static constexpr int pA1 = PA1, rA1 = RA1, pB2 = PB2, rB2 = RB2, pA3 = PA3, rA3 = RA3, pA6 = PA6,       \
+                             rA6 = RA6, pB7 = PB7, rB7 = RB7;                                                   \
+        static constexpr int sizeA = Q * cmax3(PA1, PA3, PA6), sizeB = Q * cmax3(PB2, PA3, PB7);                \
+    };
+KX_LDS(2, 2, 4, 2, 4, 2, 4, 2, 4, 2, 4, 2)
+KX_LDS(2, 3, 4, 2, 6, 2, 9, 3, 6, 2, 4, 2)
+KX_LDS(3, 3, 9, 3, 9, 3, 9, 3, 9, 3, 9, 3)
+KX_LDS(3, 4, 9, 3, 12, 3, 19, 4, 12, 3, 9, 3)
+KX_LDS(4, 4, 18, 4, 19, 4, 19, 4, 19, 4, 18, 4)
+KX_LDS(4, 5, 18, 4, 25, 5, 25, 5, 25, 5, 18, 4)
+KX_LDS(5, 5, 26, 5, 37, 7, 25, 5, 37, 7, 26, 5)
+KX_LDS(5, 6, 27, 5, 37, 6, 36, 6, 37, 6, 27, 5)
+KX_LDS(6, 6, 38, 6, 42, 7, 36, 6, 42, 7, 38, 6)
+KX_LDS(6, 7, 38, 6, 70, 7, 51, 7, 70, 7, 38, 6)
+KX_LDS(7, 7, 71, 7, 71, 8, 51, 7, 71, 8, 71, 7)
+KX_LDS(7, 8, 71, 7, 103, 12, 72, 9, 103, 12, 71, 7)
+KX_LDS(8, 8, 72, 8, 72, 9, 72, 9, 72, 9, 72, 8)
+#undef KX_LDS
+
+template <int N1, int Q1>
+__global__ __launch_bounds__(64) void kx_kernel(const KxParams a) {
+    using T = KxTab<N1, Q1>;
+    static_assert(T::total <= kPoiTab, "1D tables exceed the kernel-argument area");
+    using L = KxLds<N1, Q1>;
+    static_assert(L::rA1 >= N1 && L::pA1 >= N1 * L::rA1 && L::rB2 >= N1 && L::pB2 >= Q1 * L::rB2 &&
+                      L::rA3 >= Q1 && L::pA3 >= Q1 * L::rA3 && L::rA6 >= N1 && L::pA6 >= Q1 * L::rA6 &&
+                      L::rB7 >= N1 && L::pB7 >= N1 * L::rB7,
+                  "LDS strides must not overlap rows or planes");
+    __shared__ double A[L::sizeA], B[L::sizeB];
+    // the 1D tables are kernel arguments: after unrolling every index is a
+    // constant, so they are read through scalar loads into SGPRs
+    const double *tw = a.tab + T::W;
     const int lane = threadIdx.x;
-    for (int t = lane; t < Q1 * N1; t += 64) tN[t] = a.tab[t];
-    for (int t = lane; t < Q1 * Q1; t += 64) tD[t] = a.tab[Q1 * N1 + t];
-    if (lane < Q1) tw[lane] = a.tab[Q1 * N1 + Q1 * Q1 + lane];
     const int64_t e = xcd_remap(blockIdx.x, a.ncells);
     const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
     const int64_t NxNy = a.Nx * a.Ny;
@@ -51,35 +141,26 @@ __global__ __launch_bounds__(64) void kx_kernel(KxParams a) {
     const int li = lane % N1, lj = lane / N1;
     const int64_t base = wrap1(ex * a.p + li, a.Nx) + a.Nx * wrap1(ey * a.p + lj, a.Ny);
     const int64_t gz0 = ez * a.p;
-    __syncthreads();
 
     // 1: gather the z-line into registers and interpolate along z -> A[qz][j][i]
     if (lane < N1 * N1) {
-        double xv[N1];
+        double xv[N1], o[Q1];
 #pragma unroll
         for (int k = 0; k < N1; ++k) xv[k] = a.x[base + NxNy * wrap1(gz0 + k, a.Nz)];
+        eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, xv, o);
 #pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) {
-            double s = 0;
-#pragma unroll
-            for (int k = 0; k < N1; ++k) s += tN[qz * N1 + k] * xv[k];
-            A[(qz * N1 + lj) * N1 + li] = s;
-        }
+        for (int qz = 0; qz < Q1; ++qz) A[qz * L::pA1 + lj * L::rA1 + li] = o[qz];
     }
     __syncthreads();
     // 2: along y, lane (qz, i) -> B[qz][qy][i]
     if (lane < Q1 * N1) {
         const int qz = lane / N1, i = lane % N1;
-        double v[N1];
+        double v[N1], o[Q1];
 #pragma unroll
-        for (int j = 0; j < N1; ++j) v[j] = A[(qz * N1 + j) * N1 + i];
+        for (int j = 0; j < N1; ++j) v[j] = A[qz * L::pA1 + j * L::rA1 + i];
+        eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, v, o);
 #pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) {
-            double s = 0;
-#pragma unroll
-            for (int j = 0; j < N1; ++j) s += tN[qy * N1 + j] * v[j];
-            B[(qz * Q1 + qy) * N1 + i] = s;
-        }
+        for (int qy = 0; qy < Q1; ++qy) B[qz * L::pB2 + qy * L::rB2 + i] = o[qy];
     }
     __syncthreads();
     // 3: along x, lane (qz, qy): values at the Gauss points -> A[qz][qy][qx];
@@ -87,123 +168,79 @@ __global__ __launch_bounds__(64) void kx_kernel(KxParams a) {
     double ux[Q1];
     if (lane < Q1 * Q1) {
         const int qz = lane / Q1, qy = lane % Q1;
-        double v[N1], u[Q1];
+        double v[N1], u[Q1], g[Q1];
 #pragma unroll
-        for (int i = 0; i < N1; ++i) v[i] = B[(qz * Q1 + qy) * N1 + i];
+        for (int i = 0; i < N1; ++i) v[i] = B[qz * L::pB2 + qy * L::rB2 + i];
+        eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, v, u);
 #pragma unroll
-        for (int qx = 0; qx < Q1; ++qx) {
-            double s = 0;
+        for (int qx = 0; qx < Q1; ++qx) A[qz * L::pA3 + qy * L::rA3 + qx] = u[qx];
+        eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, u, g);
+        const double wzy = pick<Q1>(tw, qz) * pick<Q1>(tw, qy) * a.cx;
 #pragma unroll
-            for (int i = 0; i < N1; ++i) s += tN[qx * N1 + i] * v[i];
-            u[qx] = s;
-            A[(qz * Q1 + qy) * Q1 + qx] = s;
-        }
-        const double wzy = tw[qz] * tw[qy] * a.cx;
-        double g[Q1];
-#pragma unroll
-        for (int t = 0; t < Q1; ++t) {
-            double s = 0;
-#pragma unroll
-            for (int b = 0; b < Q1; ++b) s += tD[t * Q1 + b] * u[b];
-            g[t] = s * wzy * tw[t];
-        }
-#pragma unroll
-        for (int qx = 0; qx < Q1; ++qx) {
-            double s = 0;
-#pragma unroll
-            for (int t = 0; t < Q1; ++t) s += tD[t * Q1 + qx] * g[t];
-            ux[qx] = s;
-        }
+        for (int t = 0; t < Q1; ++t) g[t] *= wzy * tw[t];
+        eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, ux);
     }
     __syncthreads();
     // 4: y-gradient, lane (qz, qx) -> B[qz][qy][qx] = Dq^T (W_y dy u)
     if (lane < Q1 * Q1) {
         const int qz = lane / Q1, qx = lane % Q1;
-        double u[Q1], g[Q1];
+        double u[Q1], g[Q1], h[Q1];
 #pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) u[qy] = A[(qz * Q1 + qy) * Q1 + qx];
-        const double wzx = tw[qz] * tw[qx] * a.cy;
+        for (int qy = 0; qy < Q1; ++qy) u[qy] = A[qz * L::pA3 + qy * L::rA3 + qx];
+        eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, u, g);
+        const double wzx = pick<Q1>(tw, qz) * pick<Q1>(tw, qx) * a.cy;
 #pragma unroll
-        for (int t = 0; t < Q1; ++t) {
-            double s = 0;
+        for (int t = 0; t < Q1; ++t) g[t] *= wzx * tw[t];
+        eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, h);
 #pragma unroll
-            for (int b = 0; b < Q1; ++b) s += tD[t * Q1 + b] * u[b];
-            g[t] = s * wzx * tw[t];
-        }
-#pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) {
-            double s = 0;
-#pragma unroll
-            for (int t = 0; t < Q1; ++t) s += tD[t * Q1 + qy] * g[t];
-            B[(qz * Q1 + qy) * Q1 + qx] = s;
-        }
+        for (int qy = 0; qy < Q1; ++qy) B[qz * L::pA3 + qy * L::rA3 + qx] = h[qy];
     }
     __syncthreads();
     // 5: z-gradient, lane (qy, qx) -> B[qz][qy][qx] += Dq^T (W_z dz u)
     if (lane < Q1 * Q1) {
         const int qy = lane / Q1, qx = lane % Q1;
-        double u[Q1], g[Q1];
+        double u[Q1], g[Q1], h[Q1];
 #pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) u[qz] = A[(qz * Q1 + qy) * Q1 + qx];
-        const double wyx = tw[qy] * tw[qx] * a.cz;
+        for (int qz = 0; qz < Q1; ++qz) u[qz] = A[qz * L::pA3 + qy * L::rA3 + qx];
+        eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, u, g);
+        const double wyx = pick<Q1>(tw, qy) * pick<Q1>(tw, qx) * a.cz;
 #pragma unroll
-        for (int t = 0; t < Q1; ++t) {
-            double s = 0;
+        for (int t = 0; t < Q1; ++t) g[t] *= wyx * tw[t];
+        eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, h);
 #pragma unroll
-            for (int b = 0; b < Q1; ++b) s += tD[t * Q1 + b] * u[b];
-            g[t] = s * wyx * tw[t];
-        }
-#pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) {
-            double s = 0;
-#pragma unroll
-            for (int t = 0; t < Q1; ++t) s += tD[t * Q1 + qz] * g[t];
-            B[(qz * Q1 + qy) * Q1 + qx] += s;
-        }
+        for (int qz = 0; qz < Q1; ++qz) B[qz * L::pA3 + qy * L::rA3 + qx] += h[qz];
     }
     __syncthreads();
     // 6: lane (qz, qy): total line, back along x -> A[qz][qy][i]
     if (lane < Q1 * Q1) {
         const int qz = lane / Q1, qy = lane % Q1;
-        double s[Q1];
+        double sq[Q1], o[N1];
 #pragma unroll
-        for (int qx = 0; qx < Q1; ++qx) s[qx] = ux[qx] + B[(qz * Q1 + qy) * Q1 + qx];
+        for (int qx = 0; qx < Q1; ++qx) sq[qx] = ux[qx] + B[qz * L::pA3 + qy * L::rA3 + qx];
+        eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, sq, o);
 #pragma unroll
-        for (int i = 0; i < N1; ++i) {
-            double t = 0;
-#pragma unroll
-            for (int qx = 0; qx < Q1; ++qx) t += tN[qx * N1 + i] * s[qx];
-            A[(qz * Q1 + qy) * N1 + i] = t;
-        }
+        for (int i = 0; i < N1; ++i) A[qz * L::pA6 + qy * L::rA6 + i] = o[i];
     }
     __syncthreads();
     // 7: back along y, lane (qz, i) -> B[qz][j][i]
     if (lane < Q1 * N1) {
         const int qz = lane / N1, i = lane % N1;
-        double v[Q1];
+        double v[Q1], o[N1];
 #pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) v[qy] = A[(qz * Q1 + qy) * N1 + i];
+        for (int qy = 0; qy < Q1; ++qy) v[qy] = A[qz * L::pA6 + qy * L::rA6 + i];
+        eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, v, o);
 #pragma unroll
-        for (int j = 0; j < N1; ++j) {
-            double s = 0;
-#pragma unroll
-            for (int qy = 0; qy < Q1; ++qy) s += tN[qy * N1 + j] * v[qy];
-            B[(qz * N1 + j) * N1 + i] = s;
-        }
+        for (int j = 0; j < N1; ++j) B[qz * L::pB7 + j * L::rB7 + i] = o[j];
     }
     __syncthreads();
     // 8: back along z in registers, assembled with atomic adds
     if (lane < N1 * N1) {
-        double v[Q1];
+        double v[Q1], o[N1];
 #pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) v[qz] = B[(qz * N1 + lj) * N1 + li];
+        for (int qz = 0; qz < Q1; ++qz) v[qz] = B[qz * L::pB7 + lj * L::rB7 + li];
+        eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, v, o);
 #pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            double s = 0;
-#pragma unroll
-            for (int qz = 0; qz < Q1; ++qz) s += tN[qz * N1 + k] * v[qz];
-            atomicAdd(a.y + base + NxNy * wrap1(gz0 + k, a.Nz), s);
-        }
+        for (int k = 0; k < N1; ++k) atomicAdd(a.y + base + NxNy * wrap1(gz0 + k, a.Nz), o[k]);
     }
 }
 
@@ -369,7 +406,7 @@ static void kx_go(const KxParams &a, int64_t ncells, hipStream_t s) {
 
 bool kx_supported(int n1, int q1) { return n1 >= 2 && n1 <= 8 && (q1 == n1 || (q1 == n1 + 1 && q1 <= 8)); }
 
-hipError_t launch_kx(const chfsi_ctx *c, const double *tab, const double *x, double *y, hipStream_t s) {
+hipError_t launch_kx(const chfsi_ctx *c, const double *x, double *y, hipStream_t s) {
     const Mesh &m = c->m;
     if (!kx_supported(m.n1, m.nq1)) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(y, 0, (size_t)m.M * sizeof(double), s);
@@ -384,7 +421,7 @@ hipError_t launch_kx(const chfsi_ctx *c, const double *tab, const double *x, dou
     a.Ny = m.Nd[1];
     a.Nz = m.Nd[2];
     a.p = m.p;
-    a.tab = tab;
+    for (int i = 0; i < kPoiTab; ++i) a.tab[i] = c->poi_tab[i];
     const double detJ = m.h[0] * m.h[1] * m.h[2] / 8.0;
     a.cx = detJ * 4.0 / (m.h[0] * m.h[0]);
     a.cy = detJ * 4.0 / (m.h[1] * m.h[1]);

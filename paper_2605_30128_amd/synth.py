@@ -97,6 +97,39 @@ def quad_abscissae(nq1: int) -> np.ndarray:
     return np.sort(x)
 
 
+def gll_abscissae(p: int) -> np.ndarray:
+    """Ascending Gauss-Lobatto-Legendre nodes on [-1,1] (the FE nodes of a
+    cell, +-1 and the roots of P_p') from NumPy (sample sites)."""
+    inner = np.polynomial.legendre.Legendre.basis(p).deriv().roots() if p > 1 else np.zeros(0)
+    return np.concatenate([[-1.0], np.sort(inner.real), [1.0]])
+
+
+def node_coords(ncell, h, p: int) -> np.ndarray:
+    """Physical coordinates [M][3] of the global nodes g = gx + Nx (gy + Ny gz)
+    of the periodic mesh (node gx lies in cell gx // p at GLL node gx % p)."""
+    xi = gll_abscissae(p)
+    axes = []
+    for d in range(3):
+        g = np.arange(int(ncell[d]) * p)
+        axes.append((g // p) * h[d] + 0.5 * (xi[g % p] + 1.0) * h[d])
+    Z, Y, X = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def neutral_charge(X: np.ndarray, box, ncentres: int, seed: int, charge=4.0, width=WELL_WIDTH) -> np.ndarray:
+    """A neutral charge density sampled at the points X: `ncentres` normalised
+    Gaussians of `charge` electrons each (random centres, minimum image) minus
+    the uniform background of the same total charge."""
+    box = np.asarray(box, float)
+    centres = np.random.default_rng([seed, 6]).uniform(0.0, 1.0, size=(ncentres, 3)) * box
+    rho = np.zeros(X.shape[0])
+    norm = charge / (2 * math.pi * width ** 2) ** 1.5
+    for c in centres:
+        d = min_image(X - c, box)
+        rho += norm * np.exp(-(d * d).sum(axis=1) / (2 * width ** 2))
+    return rho - ncentres * charge / float(np.prod(box))
+
+
 def cell_quad_points(ncell, h, nq1, cells: Optional[np.ndarray] = None) -> np.ndarray:
     """Physical positions [len(cells), nq, 3] of the sample sites of the cells."""
     ncx, ncy, ncz = ncell

@@ -1,5 +1,5 @@
 """Pins of the block floating-point codec oracle against what its definition
-fixes (Sec. III-C4, compressed communication): the size of the stream, the
+fixes (Sec. III-C3, compressed communication): the size of the stream, the
 zero-block flag, the shared exponent (checked against numpy's frexp), exact
 round trips of representable values, the half-quantum error bound, the
 upper-bound clamp, ties to even, block locality and subnormal blocks."""
