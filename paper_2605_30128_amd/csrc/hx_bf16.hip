@@ -168,34 +168,46 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a) {
     }
     __syncthreads();
     {
-        // gather: every load of the thread is issued before the first LDS
-        // store; a wave reads whole 16-vector rows (128 bytes)
+        // gather: a task is (vector v, spin s, eight consecutive nodes): eight
+        // 8-byte row loads (the 16 vectors of a lane group read a 128-byte
+        // row piece), all issued before the first LDS store; the eight real
+        // parts and the eight imaginary parts then go to LDS as one 16-byte
+        // store each.  With rows KS apart the 16 stores of a pass fall on
+        // disjoint banks at NP = 352.
         const cf *X = reinterpret_cast<const cf *>(a.X);
-        constexpr int NH = VB >= 32 ? 2 : 1, HV = VB / NH, TOT = NP * 2 * HV, ITER = (TOT + kBfThreads - 1) / kBfThreads;
+        constexpr int NH = VB >= 32 ? 2 : 1, HV = VB / NH, NB8 = NP / 8;
+        constexpr int TASKS = HV * 2 * NB8, ITER = (TASKS + kBfThreads - 1) / kBfThreads;
+        static_assert(NP % 8 == 0 && (KS * 2) % 16 == 0, "16-byte node pieces");
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            cf z[ITER];
-            float sc[ITER];
+            cf z[ITER][8];
 #pragma unroll
             for (int u = 0; u < ITER; ++u) {
                 const int idx = tid + u * kBfThreads;
-                const int v = h * HV + idx % HV, s = (idx / HV) & 1, I = idx / (2 * HV);
+                const int v = h * HV + idx % HV, sp = (idx / HV) & 1, b = idx / (2 * HV);
                 const int64_t col = vb * VB + v;
-                z[u] = cf{0.f, 0.f};
-                sc[u] = 1.0f;
-                if (idx < TOT && I < a.n && col < a.nvec) {
-                    z[u] = X[(int64_t)(grow[I] + s) * a.ld + col];
-                    sc[u] = gsc[I];
+                const bool ok = idx < TASKS && col < a.nvec;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int I = 8 * b + k;
+                    z[u][k] = cf{0.f, 0.f};
+                    if (ok && I < a.n) z[u][k] = X[(int64_t)(grow[I] + sp) * a.ld + col];
                 }
             }
 #pragma unroll
             for (int u = 0; u < ITER; ++u) {
                 const int idx = tid + u * kBfThreads;
-                const int v = h * HV + idx % HV, s = (idx / HV) & 1, I = idx / (2 * HV);
-                if (idx < TOT) {
-                    xs[(4 * v + 2 * s) * KS + I] = (__bf16)(z[u].x * sc[u]);
-                    xs[(4 * v + 2 * s + 1) * KS + I] = (__bf16)(z[u].y * sc[u]);
+                const int v = h * HV + idx % HV, sp = (idx / HV) & 1, b = idx / (2 * HV);
+                if (idx >= TASKS) continue;
+                bf8 re, im;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const float sc = gsc[8 * b + k];
+                    re[k] = (__bf16)(z[u][k].x * sc);
+                    im[k] = (__bf16)(z[u][k].y * sc);
                 }
+                *reinterpret_cast<bf8 *>(xs + (4 * v + 2 * sp) * KS + 8 * b) = re;
+                *reinterpret_cast<bf8 *>(xs + (4 * v + 2 * sp + 1) * KS + 8 * b) = im;
             }
         }
     }
