@@ -157,7 +157,7 @@ def test_periodic_pde_fourier_solution(B, oracle_lib):
 
 
 def test_apply_K_full_size_slab(B, oracle_lib):
-    """K x at the largest one-GPU shape (32x32x24 cells, p = 7, 5.2M nodes),
+    """K x at the largest one-GPU shape (32x32x24 cells, p = 7, 8.4M nodes),
     all entries against the oracle."""
     print("apply_K slab 32x32x24 p=7", flush=True)
     prob = _prob((32, 32, 24), (48.0, 48.0, 36.0), 7)
@@ -200,3 +200,22 @@ def synth_charge(X, box):
         d -= box * np.round(d / box)
         rho += np.exp(-(d * d).sum(1) / (2 * 0.8 ** 2))
     return rho - rho.mean()
+
+
+def test_pcg_failure_paths(B, oracle_lib):
+    """A non-finite right-hand side is reported as CHFSI_E_NONFINITE; an upper
+    bound far below the spectrum makes the preconditioner indefinite, which
+    ends in a reported breakdown or in CHFSI_NOT_CONVERGED, never a hang."""
+    ctx = B.Chfsi(_prob((2, 2, 2), (4.0, 4.0, 4.0), 3), max_nvec=1)
+    f = torch.randn(ctx.nnodes, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    bad = f.clone()
+    bad[5] = float("nan")
+    with pytest.raises(B.ChfsiError) as ei:
+        ctx.poisson_solve(bad, tol=1e-10, max_iter=50, cheb_degree=3)
+    assert ei.value.code == B.E_NONFINITE
+    try:
+        _, rep, rc = ctx.poisson_solve(f, tol=1e-12, max_iter=200, cheb_degree=7, lambda_max=0.05)
+        assert rc in (B.OK, B.NOT_CONVERGED)
+        assert rep["iters"] <= 200
+    except B.ChfsiError as e:
+        assert e.code == B.E_NONFINITE
