@@ -419,18 +419,21 @@ int tri_inv_scaled(chfsi_ctx *c, int N, cd *L, const double *scale, cd *T, hipSt
 // (B = M A or H A).  Column-major view of a row-major block is its
 // transpose, so the upper block rows of S are S^T products Bcm Acm^H in BLAS
 // terms: one per block row of width GB, each only for the columns at and
-// right of its diagonal block (about 0.58 of the full product at N = 576).
-// The reduction dimension (2M rows) is split into nb chunks computed as one
-// strided-batched product (enough workgroups for the whole chip), the
-// partial matrices are summed in a fixed order and the strict lower
-// triangle is filled with the conjugate of the upper one.
+// right of its diagonal block (about 0.67 of the full product at N = 576).
+// The reduction dimension (2M rows) is split into up to 128 chunks computed
+// as one strided-batched product, so that even the last, narrow block row
+// gives the chip several workgroups per CU (measured on the medium mesh,
+// N = 576: 96-row blocks in 32 chunks took 50 ms more per pair of Grams than
+// 192-row blocks in 128 chunks).  The partial matrices are summed in a fixed
+// order and the strict lower triangle is filled with the conjugate of the
+// upper one.
 int gram(chfsi_ctx *c, const cd *A, const cd *B, int64_t N, int64_t ld, cd *Sm, hipStream_t s) {
-    constexpr int64_t GB = 96;
+    constexpr int64_t GB = 192;
     BLASCHK(c, rocblas_set_stream(c->blas, s));
     const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
     const int64_t rows = 2 * c->m.M;
     const size_t zcap = (c->L.scratch_bytes - c->L.Z) / sizeof(cd);
-    int64_t nb = 32;
+    int64_t nb = 128;
     while (nb > 1 && ((size_t)(nb + 1) * N * N > zcap || rows / nb < 4096)) nb /= 2;
     auto rb = [](const cd *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
     auto wb = [](cd *p) { return reinterpret_cast<rocblas_double_complex *>(p); };
