@@ -324,9 +324,9 @@ typedef struct {
 
 /* Solves K x = f' with f' = f - mean(f) (the part of f in the range of K) by
  * the PCG of Algorithm pcg_fusion (Sec. III-C1): w = K p; eta = p.w; alpha = delta/eta;
- * x += alpha p and r += alpha w in one pass; z = P^{-1} r; (delta_new,
- * gamma) = (r.z, r.r) in one reduction; beta = delta_new/delta; p = -z +
- * beta p; stop when sqrt(gamma) < tol.  r = K x - f' starts from the
+ * x += alpha p and r += alpha w in one pass; z = P^{-1} r, whose last
+ * Chebyshev step also reduces (delta_new, gamma) = (r.z, r.r); beta =
+ * delta_new/delta; p = -z + beta p; stop when sqrt(gamma) < tol.  r = K x - f' starts from the
  * caller's x (initial guess, e.g. the previous SCF step's potential), and
  * delta, eta, beta live in device memory: the host reads gamma once per
  * iteration.  Without opts->lambda_max the upper bound comes from a

@@ -1188,18 +1188,27 @@ static int read_sc(chfsi_ctx *c, hipStream_t s, double *h) {
 // delta = (b-a)/2, sigma = theta/delta, rho_0 = 1/sigma, d_0 = D^-1 r/theta;
 // rho_k = 1/(2 sigma - rho_{k-1}), d_k = rho_k rho_{k-1} d_{k-1}
 // + (2 rho_k/delta) D^-1 (r - K z_k), z_{k+1} = z_k + d_k.  d, Kz: scratch.
+// With dot_op >= 0 the last step also forms the PCG's (r.z, r.r) and
+// updates the device scalars as launch_dot2 with that op would.
 static int cheb_precond(chfsi_ctx *c, int m, double a, double b, const double *r, double *z, double *d, double *Kz,
-                        hipStream_t s) {
+                        hipStream_t s, int dot_op = -1) {
     const int64_t M = c->m.M;
     const double *dinv = c->P<double>(c->L.KdInv64);
     const double theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
     double rho = 1.0 / sigma;
-    HIPCHK(c, launch_cheb_step(M, true, 0.0, 1.0 / theta, dinv, r, nullptr, d, z, s));
-    for (int k = 1; k < m; ++k) {
-        HIPCHK(c, launch_kx(c, z, Kz, s));
-        const double rn = 1.0 / (2.0 * sigma - rho);
-        HIPCHK(c, launch_cheb_step(M, false, rn * rho, 2.0 * rn / delta, dinv, r, Kz, d, z, s));
-        rho = rn;
+    for (int k = 0; k < m; ++k) {
+        double c1 = 0.0, c2 = 1.0 / theta;
+        if (k > 0) {
+            HIPCHK(c, launch_kx(c, z, Kz, s));
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            c1 = rn * rho;
+            c2 = 2.0 * rn / delta;
+            rho = rn;
+        }
+        if (k == m - 1 && dot_op >= 0)
+            HIPCHK(c, launch_cheb_last_dot(M, k == 0, c1, c2, dinv, r, Kz, d, z, poi_part(c), dot_op, poi_sc(c), s));
+        else
+            HIPCHK(c, launch_cheb_step(M, k == 0, c1, c2, dinv, r, Kz, d, z, s));
     }
     return CHFSI_OK;
 }
@@ -1298,8 +1307,7 @@ int chfsi_poisson_solve(chfsi_ctx *c, const chfsi_pcg_opts *o, const double *f, 
     HIPCHK(c, launch_dot2(M, f, nullptr, nullptr, nullptr, part, PCG_SUMS, sc, s));
     HIPCHK(c, launch_kx(c, x, w, s));
     HIPCHK(c, launch_pcg_init(M, sc, w, f, r, s));
-    if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s))) return rc;
-    HIPCHK(c, launch_dot2(M, r, z, r, r, part, PCG_FIRST, sc, s));
+    if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s, PCG_FIRST))) return rc;
     HIPCHK(c, launch_pcg_dir(M, sc, true, z, p, s));
     if ((rc = read_sc(c, s, h))) return rc;
     int it = 0;
@@ -1309,8 +1317,8 @@ int chfsi_poisson_solve(chfsi_ctx *c, const chfsi_pcg_opts *o, const double *f, 
         HIPCHK(c, launch_kx(c, p, w, s));                                 // w = K p
         HIPCHK(c, launch_dot2(M, p, w, nullptr, nullptr, part, PCG_ETA, sc, s));  // eta = p.w
         HIPCHK(c, launch_pcg_update(M, sc, p, w, x, r, s));                    // x += a p, r += a w
-        if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s))) return rc;
-        HIPCHK(c, launch_dot2(M, r, z, r, r, part, PCG_NEXT, sc, s));          // delta, gamma, beta
+        // z = P^-1 r; the last Chebyshev step also forms delta, gamma and beta
+        if ((rc = cheb_precond(c, o->cheb_degree, lmin, lmax, r, z, d, Kz, s, PCG_NEXT))) return rc;
         HIPCHK(c, launch_pcg_dir(M, sc, false, z, p, s));                      // p = -z + beta p
         if ((rc = read_sc(c, s, h))) return rc;
         ++it;

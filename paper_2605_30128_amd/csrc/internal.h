@@ -170,6 +170,10 @@ hipError_t launch_cheb_step(int64_t n, bool first, double c1, double c2, const d
                             const double *Kz, double *d, double *z, hipStream_t s);
 hipError_t launch_axpby_real(int64_t n, double alpha, const double *x, double beta, double *y,
                              const double *scale, hipStream_t s);
+// last Chebyshev step with the (r.z, r.r) reduction of the PCG (op as in launch_dot2)
+hipError_t launch_cheb_last_dot(int64_t n, bool first, double c1, double c2, const double *dinv, const double *r,
+                                const double *Kz, const double *d, double *z, double *part, int op, double *sc,
+                                hipStream_t s);
 hipError_t launch_splitmix(int64_t n, uint64_t seed, double *v, hipStream_t s);
 hipError_t launch_sqrt(int64_t n, const double *x, double *y, hipStream_t s);
 

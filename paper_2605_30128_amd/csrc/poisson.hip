@@ -369,6 +369,38 @@ __global__ void cheb_step_kernel(int64_t n, bool first, double c1, double c2, co
     z[i] += v;
 }
 
+// The last Chebyshev step fused with the PCG's (r.z, r.r) partial sums:
+// z += c1 d + c2 D^-1 (r - K z) (first: z = c2 D^-1 r), d is not kept; the
+// grid (kDotBlocks x 256, grid-stride) and the reduction are those of
+// dot2_partial_kernel, so the partial sums are the same bits as a separate
+// pass over r and z would give.
+__global__ __launch_bounds__(256) void cheb_last_dot_kernel(int64_t n, bool first, double c1, double c2,
+                                                            const double *dinv, const double *r, const double *Kz,
+                                                            const double *d, double *z, double *part) {
+    __shared__ double s0[4], s1[4];
+    double u = 0, v = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double ri = r[i];
+        const double zi = first ? c2 * dinv[i] * ri : z[i] + (c1 * d[i] + c2 * dinv[i] * (ri - Kz[i]));
+        z[i] = zi;
+        u += ri * zi;
+        v += ri * ri;
+    }
+    u = wave_sum(u);
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s0[w] = u;
+        s1[w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = (s0[0] + s0[1]) + (s0[2] + s0[3]);
+        part[2 * blockIdx.x + 1] = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    }
+}
+
 // y = s (alpha x + beta y); x may be null (y = s beta y), s may be null (no scale)
 __global__ void axpby_real_kernel(int64_t n, double alpha, const double *x, double beta, double *y,
                                   const double *s) {
@@ -470,6 +502,15 @@ hipError_t launch_sub_mean(int64_t n, const double *sc, double *x, hipStream_t s
 hipError_t launch_cheb_step(int64_t n, bool first, double c1, double c2, const double *dinv, const double *r,
                             const double *Kz, double *d, double *z, hipStream_t s) {
     hipLaunchKernelGGL(cheb_step_kernel, g1(n), dim3(256), 0, s, n, first, c1, c2, dinv, r, Kz, d, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_cheb_last_dot(int64_t n, bool first, double c1, double c2, const double *dinv, const double *r,
+                                const double *Kz, const double *d, double *z, double *part, int op, double *sc,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(cheb_last_dot_kernel, dim3(kDotBlocks), dim3(256), 0, s, n, first, c1, c2, dinv, r, Kz, d, z,
+                       part);
+    hipLaunchKernelGGL(dot2_finish_kernel, dim3(1), dim3(256), 0, s, (const double *)part, op, sc);
     return hipGetLastError();
 }
 
