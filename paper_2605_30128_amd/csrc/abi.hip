@@ -206,6 +206,7 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
     // projection tables [pair][tile of 8 projectors][node][j % 8][spin]
     L.P64 = take((size_t)m.npairs * ((m.nbeta + 7) / 8) * m.npad * 16 * 16);
     L.P32 = take((size_t)m.npairs * ((m.nbeta + 7) / 8) * m.npad * 16 * 8);
+    L.PB = take((size_t)m.npairs * ((m.nbeta + 7) / 8) * m.npad * 64 * 2);
     L.kpad = (4 * m.nbeta + 31) / 32 * 32;
     L.WP64 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 8);
     L.WP32 = take((size_t)m.npairs * 4 * m.nbeta * m.npad * 4);

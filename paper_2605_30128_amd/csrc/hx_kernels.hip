@@ -409,6 +409,126 @@ __global__ __launch_bounds__(kThreads) void proj_kernel(ProjParams a) {
     }
 }
 
+// Projection with bfloat16 MFMA operands (the CHFSI_BF16 filter): one wave
+// owns (cell, 16 vectors) as in proj_kernel, but a v_mfma_f32_16x16x32_bf16
+// step takes eight nodes: k = 4 (node in the group) + component (x_up re,
+// x_up im, x_dn re, x_dn im), each lane supplying two nodes of its vector
+// (A) and the matching 8 k of its column (jj, re|im) of the [k][column]
+// table PB (B), built once from the FP32 projector table with the signs of
+// the complex conjugate product folded in.  Float accumulation; the partial
+// sums have the layout of the FP32 path.
+typedef __bf16 pbf8 __attribute__((ext_vector_type(8)));
+typedef float pf4 __attribute__((ext_vector_type(4)));
+
+template <int NB>
+__device__ __forceinline__ void proj_pass_bf16(const ProjParams &a, const int *gtab, const float *sc, int64_t vb16,
+                                               int u0, int pb, int lane) {
+    const int m = lane & 15, kq = lane >> 4;
+    const int64_t col = vb16 + m;
+    const bool cv = col < a.nvec;
+    const cf *X = reinterpret_cast<const cf *>(a.X);
+    const int ng = a.npad / 8;
+    const __bf16 *Q[NB];
+    int pair[NB], tile[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        pair[u] = a.cell_pairs[pb + (u0 + u) / a.ntile];
+        tile[u] = (u0 + u) % a.ntile;
+        Q[u] = reinterpret_cast<const __bf16 *>(a.P) + ((size_t)pair[u] * a.ntile + tile[u]) * ng * 512 + m * 32 + 8 * kq;
+    }
+    pf4 acc[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) acc[u] = pf4{0, 0, 0, 0};
+    const int ngroups = (a.n + 7) >> 3;
+#pragma unroll 2
+    for (int g = 0; g < ngroups; ++g) {
+        pbf8 av;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = 8 * g + 2 * kq + h;
+            cf xu{0.f, 0.f}, xd{0.f, 0.f};
+            if (cv && I < a.n) {
+                const int64_t r = 2 * (int64_t)gtab[I] * a.ld + col;
+                const float f = sc[I];
+                xu = X[r];
+                xd = X[r + a.ld];
+                xu.x *= f; xu.y *= f; xd.x *= f; xd.y *= f;
+            }
+            av[4 * h] = (__bf16)xu.x;
+            av[4 * h + 1] = (__bf16)xu.y;
+            av[4 * h + 2] = (__bf16)xd.x;
+            av[4 * h + 3] = (__bf16)xd.y;
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const pbf8 bv = *reinterpret_cast<const pbf8 *>(Q[u] + (size_t)g * 512);
+            acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[u], 0, 0, 0);
+        }
+    }
+    // accumulator: lane l, register i holds row (vector) 4*(l/16)+i, column l & 15 = (jj, re|im)
+    float *part = reinterpret_cast<float *>(a.part);
+    const int jj = m >> 1, odd = m & 1;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+        const int j = 8 * tile[u] + jj;
+        if (j >= a.nbeta) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t c = vb16 + 4 * kq + i;
+            if (c < a.nvec) part[(((size_t)pair[u] * a.nbeta + j) * a.nvec + c) * 2 + odd] = acc[u][i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void proj_kernel_bf16(ProjParams a) {
+    __shared__ int gtab[kProjMaxNodes];
+    __shared__ float sc[kProjMaxNodes];
+    const int64_t nvb = (a.nvec + 63) / 64;  // 64 vectors per workgroup, 16 per wave
+    const int64_t t_log = xcd_remap(blockIdx.x, a.ncl * nvb);
+    const int64_t ci = t_log / nvb, vb = t_log - ci * nvb;
+    const int64_t e = a.cells[ci];
+    const int64_t ex = e % a.ncx, ey = (e / a.ncx) % a.ncy, ez = e / (a.ncx * a.ncy);
+    const float *dinv = (a.flags & FLAG_DINV) ? reinterpret_cast<const float *>(a.dinv) : nullptr;
+    for (int I = threadIdx.x; I < a.n; I += kThreads) {
+        const int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
+        const int64_t g = gnode_of(i | (j << 8) | (k << 16), ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+        gtab[I] = (int)g;
+        sc[I] = dinv ? dinv[g] : 1.0f;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t vb16 = vb * 64 + wave * 16;
+    if (vb16 >= a.nvec) return;
+    const int pb = a.cell_pair_ptr[e];
+    const int nunits = (a.cell_pair_ptr[e + 1] - pb) * a.ntile;
+    for (int u0 = 0; u0 < nunits; u0 += kProjMaxUnits) {
+        switch (min(kProjMaxUnits, nunits - u0)) {
+            case 1: proj_pass_bf16<1>(a, gtab, sc, vb16, u0, pb, lane); break;
+            case 2: proj_pass_bf16<2>(a, gtab, sc, vb16, u0, pb, lane); break;
+            case 3: proj_pass_bf16<3>(a, gtab, sc, vb16, u0, pb, lane); break;
+            default: proj_pass_bf16<4>(a, gtab, sc, vb16, u0, pb, lane); break;
+        }
+    }
+}
+
+// PB[pair][tile][g][c][k] (bfloat16, g = node group of 8, c = (jj, re|im),
+// k = 4 (node in group) + component): the coefficient of component k of x in
+// the real (c even) or imaginary (c odd) part of conj(P_{I,j}) . x, from the
+// FP32 table P32[pair][tile][I][jj][spin]
+__global__ void setup_projb_kernel(const cf *P32, __bf16 *PB, int64_t total, int NP) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int k = (int)(idx & 31), c = (int)((idx >> 5) & 15);
+    const int64_t rest = idx >> 9;  // (pair * ntile + tile) * (NP / 8) + g
+    const int64_t pt = rest / (NP / 8), g = rest - pt * (NP / 8);
+    const int I = 8 * (int)g + (k >> 2), comp = k & 3, jj = c >> 1, odd = c & 1;
+    const cf pz = P32[(pt * NP + I) * 16 + 2 * jj + (comp >> 1)];
+    float v;
+    if ((comp & 1) == 0) v = odd ? -pz.y : pz.x;  // coefficient of the real part of x
+    else v = odd ? pz.x : pz.y;                    // coefficient of the imaginary part
+    PB[idx] = (__bf16)v;
+}
+
 // dcoef[atom][i][col] = sum_j Delta[atom][i][j] * sum_{pairs of atom} part[pair][j][col]
 template <typename TC>
 __global__ void nl_reduce_kernel(const TC *part, const int *atom_pair_ptr, const cd *delta,
@@ -672,7 +792,7 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
 
 template <typename T>
 static hipError_t run_proj(const chfsi_ctx *c, int flags, const void *X, int64_t nvec, int64_t ld,
-                           hipStream_t s) {
+                           hipStream_t s, bool bf16 = false) {
     const Mesh &m = c->m;
     const Layout &L = c->L;
     constexpr bool dbl = sizeof(T) == 8;
@@ -693,7 +813,12 @@ static hipError_t run_proj(const chfsi_ctx *c, int flags, const void *X, int64_t
     a.ntile = (m.nbeta + 7) / 8;
     a.flags = flags;
     const int64_t nvb = (nvec + 63) / 64;
-    hipLaunchKernelGGL((proj_kernel<T>), dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
+    if (bf16) {
+        a.P = c->P<char>(L.PB);
+        hipLaunchKernelGGL(proj_kernel_bf16, dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((proj_kernel<T>), dim3((unsigned)(a.ncl * nvb)), dim3(kThreads), 0, s, a);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int64_t nthr = m.natoms * nvec;
@@ -752,7 +877,7 @@ hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags
                                   int64_t nvec, int64_t ld, hipStream_t s) {
     if (c->m.npairs == 0 || c->m.n_nl_cells == 0) return hipSuccess;
     if (prec == CHFSI_FP64) return run_proj<double>(c, flags, X, nvec, ld, s);
-    return run_proj<float>(c, flags, X, nvec, ld, s);
+    return run_proj<float>(c, flags, X, nvec, ld, s, prec == CHFSI_BF16);
 }
 
 hipError_t launch_adjoint_fields(const chfsi_ctx *c, chfsi_prec prec, const void *X, const void *G,
@@ -778,6 +903,9 @@ hipError_t launch_setup_projectors(const chfsi_ctx *c, const cd *phi_dev, hipStr
     hipLaunchKernelGGL(setup_proj_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s, phi_dev,
                        c->P<double>(c->L.Phi64), c->P<double>(c->L.Wq), c->P<cd>(c->L.P64),
                        c->P<cf>(c->L.P32), m.npairs, m.n, m.nq, m.npad, m.nbeta);
+    const int64_t nb = m.npairs * ((m.nbeta + 7) / 8) * m.npad * 64;
+    hipLaunchKernelGGL(setup_projb_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, c->P<cf>(c->L.P32),
+                       c->P<__bf16>(c->L.PB), nb, m.npad);
     const int64_t nw = m.npairs * m.npad * c->L.kpad;
     hipLaunchKernelGGL(setup_wphi_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, phi_dev,
                        c->P<double>(c->L.Wq), c->P<double>(c->L.WP64), c->P<float>(c->L.WP32),

@@ -42,6 +42,7 @@ struct Layout {
     size_t cell_pair_ptr, cell_pairs;        // int32 [ncells+1], [npairs]
     size_t pair_atom, atom_pair_ptr;         // int32 [npairs], [natoms+1]
     size_t P64, P32;                         // complex [npairs][npad][2][nbeta]
+    size_t PB;                               // bfloat16 [npairs][tile][npad/8][16][32]: projection B operand
     size_t WP64, WP32;                       // real [npairs][4 nbeta][npad]: w|J| phi, k = (j, spin, re|im)
     size_t WPb;                              // bfloat16 [npairs][npad][kpad]: same, k contiguous
     int kpad;                                // 4 nbeta rounded up to 32
