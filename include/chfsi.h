@@ -34,9 +34,9 @@
  * Precision   CHFSI_FP64: all products in double on FP64 MFMA.
  *             CHFSI_FP32: cell GEMMs and projector products with float
  *             operands on FP32 MFMA, float accumulation.
- *             CHFSI_BF16: cell-GEMM operands rounded to bfloat16 (nearest
- *             even), float accumulation on BF16 MFMA; pointwise and
- *             projector terms in float.
+ *             CHFSI_BF16: cell-GEMM and projector-product operands rounded
+ *             to bfloat16 (nearest even), float accumulation on BF16 MFMA;
+ *             the pointwise 2x2 spin term and Delta in float.
  *             The residual, the Chebyshev scalars, orthonormalization and
  *             Rayleigh-Ritz always run in double (Sec. III-C2).
  * Memory      The caller owns every device buffer.  chfsi_plan reports the
