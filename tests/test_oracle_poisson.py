@@ -170,3 +170,15 @@ def test_periodic_poisson_fourier_solution(oracle_lib):
     x, it, conv, _ = poisson.pcg(K, f, np.zeros(K.M), 1e-12, 1000, 5, b / 20, b)
     assert conv
     assert np.abs(x - (u - u.mean())).max() < 1e-4
+
+
+def test_synth_node_coordinates_match_the_oracle(oracle_lib):
+    """The benchmark's input generator places the nodes where the oracle's
+    GLL rule puts them (same global numbering)."""
+    for p in range(1, 8):
+        assert np.allclose(synth.gll_abscissae(p), oracle_lib.gll(p)[0], rtol=0, atol=1e-14)
+    prob = _prob(ncell=(2, 4, 2), box=(3.0, 6.0, 5.0), degree=3)
+    assert np.allclose(synth.node_coords(prob.ncell, prob.h, prob.degree), node_coords(oracle_lib, prob),
+                       rtol=0, atol=1e-13)
+    rho = synth.neutral_charge(node_coords(oracle_lib, prob), prob.box, ncentres=3, seed=2)
+    assert rho.shape == (prob.nnodes,) and np.isfinite(rho).all()
