@@ -529,33 +529,43 @@ __global__ void setup_projb_kernel(const cf *P32, __bf16 *PB, int64_t total, int
     PB[idx] = (__bf16)v;
 }
 
-// dcoef[atom][i][col] = sum_j Delta[atom][i][j] * sum_{pairs of atom} part[pair][j][col]
+// dcoef[atom][i][col] = sum_j Delta[atom][i][j] * sum_{pairs of atom} part[pair][j][col].
+// A workgroup owns one atom and 64 columns; thread (j, col) sums projector j
+// over the atom's pairs (in pair order, coalesced over the columns), the
+// sums meet in LDS, and thread (i, col) applies row i of Delta.
+constexpr int kNlCols = 64;
+
 template <typename TC>
-__global__ void nl_reduce_kernel(const TC *part, const int *atom_pair_ptr, const cd *delta,
-                                 TC *dcoef, int64_t natoms, int nbeta, int64_t nvec) {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= natoms * nvec) return;
-    int64_t atom = idx / nvec, col = idx % nvec;
-    double sr[kMaxBeta], si[kMaxBeta];
-    for (int j = 0; j < nbeta; ++j) { sr[j] = 0; si[j] = 0; }
-    for (int pr = atom_pair_ptr[atom]; pr < atom_pair_ptr[atom + 1]; ++pr)
-        for (int j = 0; j < nbeta; ++j) {
-            TC v = part[((size_t)pr * nbeta + j) * nvec + col];
-            sr[j] += v.x;
-            si[j] += v.y;
+__global__ __launch_bounds__(kNlCols * kMaxBeta) void nl_reduce_kernel(const TC *part, const int *atom_pair_ptr,
+                                                                       const cd *delta, TC *dcoef, int nbeta,
+                                                                       int64_t nvec) {
+    __shared__ double sr[kMaxBeta][kNlCols], si[kMaxBeta][kNlCols];
+    const int64_t atom = blockIdx.x;
+    const int cl = threadIdx.x % kNlCols, j = threadIdx.x / kNlCols;
+    const int64_t col = (int64_t)blockIdx.y * kNlCols + cl;
+    double ar = 0, ai = 0;
+    if (col < nvec)
+        for (int pr = atom_pair_ptr[atom]; pr < atom_pair_ptr[atom + 1]; ++pr) {
+            const TC v = part[((size_t)pr * nbeta + j) * nvec + col];
+            ar += v.x;
+            ai += v.y;
         }
-    const cd *D = delta + (size_t)atom * nbeta * nbeta;
-    for (int i = 0; i < nbeta; ++i) {
-        double ar = 0, ai = 0;
-        for (int j = 0; j < nbeta; ++j) {
-            cd d = D[i * nbeta + j];
-            ar += d.x * sr[j] - d.y * si[j];
-            ai += d.x * si[j] + d.y * sr[j];
-        }
-        TC o;
-        o.x = ar; o.y = ai;
-        dcoef[((size_t)atom * nbeta + i) * nvec + col] = o;
+    sr[j][cl] = ar;
+    si[j][cl] = ai;
+    __syncthreads();
+    if (col >= nvec) return;
+    const int i = j;
+    const cd *D = delta + ((size_t)atom * nbeta + i) * nbeta;
+    double xr = 0, xi = 0;
+    for (int jj = 0; jj < nbeta; ++jj) {
+        const cd d = D[jj];
+        xr += d.x * sr[jj][cl] - d.y * si[jj][cl];
+        xi += d.x * si[jj][cl] + d.y * sr[jj][cl];
     }
+    TC o;
+    o.x = xr;
+    o.y = xi;
+    dcoef[((size_t)atom * nbeta + i) * nvec + col] = o;
 }
 
 // ---------------------------------------------------------------------------
@@ -821,15 +831,13 @@ static hipError_t run_proj(const chfsi_ctx *c, int flags, const void *X, int64_t
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    const int64_t nthr = m.natoms * nvec;
+    const dim3 grd((unsigned)m.natoms, (unsigned)((nvec + kNlCols - 1) / kNlCols));
     if (dbl)
-        hipLaunchKernelGGL(nl_reduce_kernel<cd>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s,
-                           c->S<cd>(L.partial), c->P<int>(L.atom_pair_ptr), c->P<cd>(L.delta64),
-                           c->S<cd>(L.dcoef), m.natoms, m.nbeta, nvec);
+        hipLaunchKernelGGL(nl_reduce_kernel<cd>, grd, dim3(kNlCols * m.nbeta), 0, s, c->S<cd>(L.partial),
+                           c->P<int>(L.atom_pair_ptr), c->P<cd>(L.delta64), c->S<cd>(L.dcoef), m.nbeta, nvec);
     else
-        hipLaunchKernelGGL(nl_reduce_kernel<cf>, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, s,
-                           c->S<cf>(L.partial), c->P<int>(L.atom_pair_ptr), c->P<cd>(L.delta64),
-                           c->S<cf>(L.dcoef), m.natoms, m.nbeta, nvec);
+        hipLaunchKernelGGL(nl_reduce_kernel<cf>, grd, dim3(kNlCols * m.nbeta), 0, s, c->S<cf>(L.partial),
+                           c->P<int>(L.atom_pair_ptr), c->P<cd>(L.delta64), c->S<cf>(L.dcoef), m.nbeta, nvec);
     return hipGetLastError();
 }
 
