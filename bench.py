@@ -8,9 +8,12 @@ the timed steps processed per second (q products of the nsub-column block per
 iteration), i.e. whole-job H X throughput including the Rayleigh-Ritz stage.
 Isolated H X throughputs per precision, the double-precision iteration
 time, the roofline of the dominant kernel and the CPU oracle baseline are
-reported beside it.
+reported beside it, together with the block floating-point codec's
+throughput and the Poisson workload (matrix-free K x throughput with its
+roofline, PCG time to an absolute residual of 1e-10).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16|fp32]
+python bench.py --poisson-only | --hx-only | --converge [--precs fp64,bf16,fp32]
 """
 from __future__ import annotations
 
