@@ -1,5 +1,7 @@
 // Matrix-free cell-level Hamiltonian-times-multivector product for gfx950
-// (double and float MFMA; the bfloat16 variant is in hx_bf16.hip).
+// (double and float MFMA; the bfloat16 cell kernel is in hx_bf16.hip), the
+// spin-orbit projection kernels of every precision (the bfloat16 one
+// included), the per-atom reduction with Delta, and the adjoint.
 //
 // Stages follow the paper's product (Sec. III-C2, stages i-iv): gather of the
 // cell block, dense cell contraction, spin-orbit projector term, assembly.
