@@ -103,7 +103,7 @@ template <int N1, int Q1> struct KxLds;
     template <> struct KxLds<N, Q> {                                                                            \
         static constexpr int pA1 = PA1, rA1 = RA1, pB2 = PB2, rB2 = RB2, pA3 = PA3, rA3 = RA3, pA6 = PA6,       \
                              rA6 = RA6, pB7 = PB7, rB7 = RB7;                                                   \
-        static constexpr int sizeA = Q * cmax3(PA1, PA3, PA6), sizeB = Q * cmax3(PB2, PA3, PB7);                \
+        static constexpr int size = Q * cmax3(cmax3(PA1, PA3, PA6), PB2, PB7);                                  \
     };
 KX_LDS(2, 2, 4, 2, 4, 2, 4, 2, 4, 2, 4, 2)
 KX_LDS(2, 3, 4, 2, 6, 2, 9, 3, 6, 2, 4, 2)
@@ -129,7 +129,11 @@ __global__ __launch_bounds__(64) void kx_kernel(const KxParams a) {
                       L::rA3 >= Q1 && L::pA3 >= Q1 * L::rA3 && L::rA6 >= N1 && L::pA6 >= Q1 * L::rA6 &&
                       L::rB7 >= N1 && L::pB7 >= N1 * L::rB7,
                   "LDS strides must not overlap rows or planes");
-    __shared__ double A[L::sizeA], B[L::sizeB];
+    // one LDS cube, re-laid out by every phase: each phase reads its lines
+    // into registers, waits, then writes its results over the cube, so a
+    // wave needs a single cube (the barriers of a one-wave workgroup are
+    // nearly free) and more waves fit a CU
+    __shared__ double C[L::size];
     // the 1D tables are kernel arguments: after unrolling every index is a
     // constant, so they are read through scalar loads into SGPRs
     const double *tw = a.tab + T::W;
@@ -142,102 +146,131 @@ __global__ __launch_bounds__(64) void kx_kernel(const KxParams a) {
     const int64_t base = wrap1(ex * a.p + li, a.Nx) + a.Nx * wrap1(ey * a.p + lj, a.Ny);
     const int64_t gz0 = ez * a.p;
 
-    // 1: gather the z-line into registers and interpolate along z -> A[qz][j][i]
+    // 1: gather the z-line into registers and interpolate along z -> C[qz][j][i]
     if (lane < N1 * N1) {
         double xv[N1], o[Q1];
 #pragma unroll
         for (int k = 0; k < N1; ++k) xv[k] = a.x[base + NxNy * wrap1(gz0 + k, a.Nz)];
         eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, xv, o);
 #pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) A[qz * L::pA1 + lj * L::rA1 + li] = o[qz];
+        for (int qz = 0; qz < Q1; ++qz) C[qz * L::pA1 + lj * L::rA1 + li] = o[qz];
     }
     __syncthreads();
-    // 2: along y, lane (qz, i) -> B[qz][qy][i]
-    if (lane < Q1 * N1) {
+    // 2: along y, lane (qz, i) -> C[qz][qy][i]
+    {
         const int qz = lane / N1, i = lane % N1;
+        const bool act = lane < Q1 * N1;
         double v[N1], o[Q1];
+        if (act) {
 #pragma unroll
-        for (int j = 0; j < N1; ++j) v[j] = A[qz * L::pA1 + j * L::rA1 + i];
-        eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, v, o);
+            for (int j = 0; j < N1; ++j) v[j] = C[qz * L::pA1 + j * L::rA1 + i];
+        }
+        __syncthreads();
+        if (act) {
+            eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, v, o);
 #pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) B[qz * L::pB2 + qy * L::rB2 + i] = o[qy];
+            for (int qy = 0; qy < Q1; ++qy) C[qz * L::pB2 + qy * L::rB2 + i] = o[qy];
+        }
     }
     __syncthreads();
-    // 3: along x, lane (qz, qy): values at the Gauss points -> A[qz][qy][qx];
+    // 3: along x, lane (qz, qy): values at the Gauss points -> C[qz][qy][qx];
     //    the x-gradient line and its transposed derivative stay in registers
     double ux[Q1];
-    if (lane < Q1 * Q1) {
+    {
         const int qz = lane / Q1, qy = lane % Q1;
+        const bool act = lane < Q1 * Q1;
         double v[N1], u[Q1], g[Q1];
+        if (act) {
 #pragma unroll
-        for (int i = 0; i < N1; ++i) v[i] = B[qz * L::pB2 + qy * L::rB2 + i];
-        eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, v, u);
+            for (int i = 0; i < N1; ++i) v[i] = C[qz * L::pB2 + qy * L::rB2 + i];
+        }
+        __syncthreads();
+        if (act) {
+            eo_apply<N1, Q1, 1>(a.tab + T::NE, a.tab + T::NO, v, u);
 #pragma unroll
-        for (int qx = 0; qx < Q1; ++qx) A[qz * L::pA3 + qy * L::rA3 + qx] = u[qx];
-        eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, u, g);
-        const double wzy = pick<Q1>(tw, qz) * pick<Q1>(tw, qy) * a.cx;
+            for (int qx = 0; qx < Q1; ++qx) C[qz * L::pA3 + qy * L::rA3 + qx] = u[qx];
+            eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, u, g);
+            const double wzy = pick<Q1>(tw, qz) * pick<Q1>(tw, qy) * a.cx;
 #pragma unroll
-        for (int t = 0; t < Q1; ++t) g[t] *= wzy * tw[t];
-        eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, ux);
+            for (int t = 0; t < Q1; ++t) g[t] *= wzy * tw[t];
+            eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, ux);
+        }
     }
     __syncthreads();
-    // 4: y-gradient, lane (qz, qx) -> B[qz][qy][qx] = Dq^T (W_y dy u)
-    if (lane < Q1 * Q1) {
-        const int qz = lane / Q1, qx = lane % Q1;
-        double u[Q1], g[Q1], h[Q1];
+    // 4, 5: lane (b, qx) reads the y-line (qz = b) and the z-line (qy = b) of
+    //    the values, then writes Dq^T (W_y dy u) over the cube and adds
+    //    Dq^T (W_z dz u) to it
+    {
+        const int b = lane / Q1, qx = lane % Q1;
+        const bool act = lane < Q1 * Q1;
+        double uy[Q1], uz[Q1], g[Q1], h[Q1];
+        if (act) {
 #pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) u[qy] = A[qz * L::pA3 + qy * L::rA3 + qx];
-        eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, u, g);
-        const double wzx = pick<Q1>(tw, qz) * pick<Q1>(tw, qx) * a.cy;
+            for (int t = 0; t < Q1; ++t) {
+                uy[t] = C[b * L::pA3 + t * L::rA3 + qx];
+                uz[t] = C[t * L::pA3 + b * L::rA3 + qx];
+            }
+        }
+        __syncthreads();
+        const double wb = pick<Q1>(tw, b) * pick<Q1>(tw, qx);
+        if (act) {
+            eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, uy, g);
 #pragma unroll
-        for (int t = 0; t < Q1; ++t) g[t] *= wzx * tw[t];
-        eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, h);
+            for (int t = 0; t < Q1; ++t) g[t] *= wb * a.cy * tw[t];
+            eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, h);
 #pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) B[qz * L::pA3 + qy * L::rA3 + qx] = h[qy];
+            for (int qy = 0; qy < Q1; ++qy) C[b * L::pA3 + qy * L::rA3 + qx] = h[qy];
+        }
+        __syncthreads();
+        if (act) {
+            eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, uz, g);
+#pragma unroll
+            for (int t = 0; t < Q1; ++t) g[t] *= wb * a.cz * tw[t];
+            eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, h);
+#pragma unroll
+            for (int qz = 0; qz < Q1; ++qz) C[qz * L::pA3 + b * L::rA3 + qx] += h[qz];
+        }
     }
     __syncthreads();
-    // 5: z-gradient, lane (qy, qx) -> B[qz][qy][qx] += Dq^T (W_z dz u)
-    if (lane < Q1 * Q1) {
-        const int qy = lane / Q1, qx = lane % Q1;
-        double u[Q1], g[Q1], h[Q1];
-#pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) u[qz] = A[qz * L::pA3 + qy * L::rA3 + qx];
-        eo_apply<Q1, Q1, -1>(a.tab + T::DE, a.tab + T::DO, u, g);
-        const double wyx = pick<Q1>(tw, qy) * pick<Q1>(tw, qx) * a.cz;
-#pragma unroll
-        for (int t = 0; t < Q1; ++t) g[t] *= wyx * tw[t];
-        eo_apply<Q1, Q1, -1>(a.tab + T::XE, a.tab + T::XO, g, h);
-#pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) B[qz * L::pA3 + qy * L::rA3 + qx] += h[qz];
-    }
-    __syncthreads();
-    // 6: lane (qz, qy): total line, back along x -> A[qz][qy][i]
-    if (lane < Q1 * Q1) {
+    // 6: lane (qz, qy): total line, back along x -> C[qz][qy][i]
+    {
         const int qz = lane / Q1, qy = lane % Q1;
+        const bool act = lane < Q1 * Q1;
         double sq[Q1], o[N1];
+        if (act) {
 #pragma unroll
-        for (int qx = 0; qx < Q1; ++qx) sq[qx] = ux[qx] + B[qz * L::pA3 + qy * L::rA3 + qx];
-        eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, sq, o);
+            for (int qx = 0; qx < Q1; ++qx) sq[qx] = ux[qx] + C[qz * L::pA3 + qy * L::rA3 + qx];
+        }
+        __syncthreads();
+        if (act) {
+            eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, sq, o);
 #pragma unroll
-        for (int i = 0; i < N1; ++i) A[qz * L::pA6 + qy * L::rA6 + i] = o[i];
+            for (int i = 0; i < N1; ++i) C[qz * L::pA6 + qy * L::rA6 + i] = o[i];
+        }
     }
     __syncthreads();
-    // 7: back along y, lane (qz, i) -> B[qz][j][i]
-    if (lane < Q1 * N1) {
+    // 7: back along y, lane (qz, i) -> C[qz][j][i]
+    {
         const int qz = lane / N1, i = lane % N1;
+        const bool act = lane < Q1 * N1;
         double v[Q1], o[N1];
+        if (act) {
 #pragma unroll
-        for (int qy = 0; qy < Q1; ++qy) v[qy] = A[qz * L::pA6 + qy * L::rA6 + i];
-        eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, v, o);
+            for (int qy = 0; qy < Q1; ++qy) v[qy] = C[qz * L::pA6 + qy * L::rA6 + i];
+        }
+        __syncthreads();
+        if (act) {
+            eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, v, o);
 #pragma unroll
-        for (int j = 0; j < N1; ++j) B[qz * L::pB7 + j * L::rB7 + i] = o[j];
+            for (int j = 0; j < N1; ++j) C[qz * L::pB7 + j * L::rB7 + i] = o[j];
+        }
     }
     __syncthreads();
     // 8: back along z in registers, assembled with atomic adds
     if (lane < N1 * N1) {
         double v[Q1], o[N1];
 #pragma unroll
-        for (int qz = 0; qz < Q1; ++qz) v[qz] = B[qz * L::pB7 + lj * L::rB7 + li];
+        for (int qz = 0; qz < Q1; ++qz) v[qz] = C[qz * L::pB7 + lj * L::rB7 + li];
         eo_apply<Q1, N1, 1>(a.tab + T::TE, a.tab + T::TO, v, o);
 #pragma unroll
         for (int k = 0; k < N1; ++k) atomicAdd(a.y + base + NxNy * wrap1(gz0 + k, a.Nz), o[k]);
