@@ -14,7 +14,8 @@
 // One wave per cell.  A lane owns one 1D line of the cube in each phase, so
 // the three gradient lines and their transposed derivatives stay in
 // registers (the paper's register/shared-memory hybrid); only the values at
-// the Gauss points and the partial sums pass through two LDS planes.  The
+// the Gauss points and the partial sums pass through one LDS cube, which
+// every phase reads into registers and then overwrites.  The
 // gather of the first phase goes straight into registers (one z-line per
 // lane) and the last contraction is assembled from registers with FP64
 // atomic adds, so y is zeroed first.
@@ -90,10 +91,11 @@ __device__ __forceinline__ double pick(const double *w, int idx) {
     return r;
 }
 
-// LDS layout of the kernel's six intermediate cubes: plane (qz) stride P
+// The five layouts the kernel's LDS cube takes in turn: plane (qz) stride P
 // and row stride R in doubles, for X[qz][row][col] at qz P + row R + col.
-// A1 = z-interpolated nodes [qz][j][i], B2 = [qz][qy][i], A3 (and B4) =
-// Gauss-point values [qz][qy][qx], A6 = [qz][qy][i], B7 = [qz][j][i].  The
+// A1 = z-interpolated nodes [qz][j][i], B2 = [qz][qy][i], A3 = Gauss-point
+// values [qz][qy][qx] (then the gradient terms), A6 = [qz][qy][i],
+// B7 = [qz][j][i].  The
 // strides are chosen so that the 64-bit accesses of each phase (lanes
 // running over two of the three indices) spread over the 64 LDS banks:
 // at most two lanes of a 32-lane pass share a bank (the unpadded cubes
