@@ -105,15 +105,15 @@ def test_lanczos_bound_parity(B, oracle_lib):
     from oracle import poisson
     ctx, K, _ = _setup(B, _prob((4, 4, 4), (6.0, 6.0, 6.0), 3), oracle_lib)
     f = _dev(np.random.default_rng(1).standard_normal(K.M))
-    _, rep, rc = ctx.poisson_solve(f, max_iter=0, lanczos_steps=20)
+    _, rep, rc = ctx.poisson_solve(f, max_iter=0, lanczos_steps=20, range_=20.0)
     assert rc == B.NOT_CONVERGED and rep["iters"] == 0
     ref = poisson.lanczos_bound(K, 20)
     assert abs(rep["lambda_max"] - ref) <= 1e-9 * ref
     assert abs(rep["lambda_min"] - rep["lambda_max"] / 20.0) <= 1e-15 * ref
 
 
-@pytest.mark.parametrize("cheb_degree", [1, 5])
-def test_pcg_parity(B, oracle_lib, cheb_degree):
+@pytest.mark.parametrize("cheb_degree,rng_", [(1, 20.0), (5, 20.0), (5, 300.0)])
+def test_pcg_parity(B, oracle_lib, cheb_degree, rng_):
     """Same interval on both sides: the same iteration count (+-1) and the same
     solution within what the residual tolerance leaves open."""
     from oracle import poisson
@@ -122,9 +122,10 @@ def test_pcg_parity(B, oracle_lib, cheb_degree):
     f = rng.standard_normal(K.M) + 0.3
     lmax = poisson.lanczos_bound(K, 20)
     tol = 1e-10 * np.linalg.norm(f)
-    xr, itr, convr, hist = poisson.pcg(K, f, np.zeros(K.M), tol, 2000, cheb_degree, lmax / 20, lmax)
+    xr, itr, convr, hist = poisson.pcg(K, f, np.zeros(K.M), tol, 2000, cheb_degree, lmax / rng_, lmax)
     assert convr
-    x, rep, rc = ctx.poisson_solve(_dev(f), tol=tol, max_iter=2000, cheb_degree=cheb_degree, lambda_max=lmax)
+    x, rep, rc = ctx.poisson_solve(_dev(f), tol=tol, max_iter=2000, cheb_degree=cheb_degree, lambda_max=lmax,
+                                   range_=rng_)
     assert rc == B.OK and rep["converged"] == 1
     assert abs(rep["iters"] - itr) <= 1
     x = x.cpu().numpy()
@@ -134,7 +135,8 @@ def test_pcg_parity(B, oracle_lib, cheb_degree):
     res = K.apply(x) - (f - f.mean())
     assert np.linalg.norm(res) < 10 * tol
     # a warm start at the solution needs no iteration
-    x2, rep2, rc2 = ctx.poisson_solve(_dev(f), x=_dev(xr), tol=tol * 100, cheb_degree=cheb_degree, lambda_max=lmax)
+    x2, rep2, rc2 = ctx.poisson_solve(_dev(f), x=_dev(xr), tol=tol * 100, cheb_degree=cheb_degree, lambda_max=lmax,
+                                      range_=rng_)
     assert rc2 == B.OK and rep2["iters"] == 0
 
 
