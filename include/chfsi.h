@@ -114,13 +114,16 @@ int chfsi_plan(const chfsi_mesh *mesh, const chfsi_projectors *proj, int64_t max
 /* Builds the operator tables (Sec. III-A quadrature; Sec. III-C2 cell
  * matrices) into `persistent` and returns a context.  V, B: device fields
  * as above (copied into the tables; the caller may free them afterwards).
- * proj may be NULL (no spin-orbit term).  Synchronizes `stream`. */
+ * proj may be NULL (no spin-orbit term).  Synchronizes `stream`.  Returns
+ * CHFSI_E_NONFINITE (and no context) if V or B holds NaN or Inf. */
 int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B,
                 const chfsi_projectors *proj, int64_t max_nvec,
                 void *persistent, size_t persistent_bytes,
                 void *scratch, size_t scratch_bytes, void *stream, chfsi_ctx **out);
 
-/* Replaces the fields V, B (device) of an existing context (same mesh). */
+/* Replaces the fields V, B (device) of an existing context (same mesh).
+ * Synchronizes; CHFSI_E_NONFINITE if V or B holds NaN or Inf, in which case
+ * the context keeps its previous fields. */
 int chfsi_set_fields(chfsi_ctx *ctx, const double *V, const double *B, void *stream);
 
 /* Y = H X (Sec. III-C2: gather, cell contraction, spin-orbit projectors,
@@ -241,7 +244,12 @@ int chfsi_solve_workspace(chfsi_ctx *ctx, int64_t nsub, int64_t ld, size_t *byte
  * H Y and M Y in double, Cholesky-QR2, Rayleigh-Ritz.  eigvals: host
  * [n_wanted] (ascending).  hist_res: optional host [max_iter+1] of the max
  * wanted residual per iteration.  Synchronizes once per iteration.
- * Returns CHFSI_OK, CHFSI_NOT_CONVERGED, or an error. */
+ * Returns CHFSI_OK, CHFSI_NOT_CONVERGED, or an error: CHFSI_E_NONFINITE if
+ * the start block (first nsub columns) or a residual holds NaN or Inf,
+ * CHFSI_E_DIVERGED if the largest wanted residual grows past 1e6 times its
+ * first value (and past 1), the symptom of a lambda_max below the top of
+ * the spectrum, CHFSI_E_BOUNDS if a Ritz value reaches lambda_max,
+ * CHFSI_E_NOT_SPD if the filtered block loses rank. */
 int chfsi_solve(chfsi_ctx *ctx, int64_t n_wanted, const chfsi_solve_opts *opts,
                 void *X, int64_t nsub, int64_t ld, const void *v0,
                 double *eigvals, double *hist_res, chfsi_report *report,

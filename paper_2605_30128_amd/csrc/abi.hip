@@ -727,7 +727,22 @@ int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B, const 
     c->scr = static_cast<char *>(scratch);
     c->blas = nullptr;
     hipStream_t s = S(stream);
-
+    {
+        // the fields must be finite (checked on the device before anything is built)
+        int *flag = c->S<int>(L.flag);
+        hipError_t fe = hipMemsetAsync(flag, 0, sizeof(int), s);
+        if (fe == hipSuccess) fe = launch_check_finite(V, m.ncells * m.nq, flag, s);
+        if (fe == hipSuccess) fe = launch_check_finite(B, m.ncells * m.nq * 3, flag, s);
+        int f = 0;
+        if (fe == hipSuccess) fe = hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (fe == hipSuccess) fe = hipStreamSynchronize(s);
+        if (fe != hipSuccess || f) {
+            const std::string em = fe != hipSuccess ? std::string("setup failed: ") + hipGetErrorString(fe)
+                                                    : std::string("V or B holds NaN or Inf");
+            delete c;
+            return fail(nullptr, fe != hipSuccess ? CHFSI_E_DEVICE : CHFSI_E_NONFINITE, em);
+        }
+    }
     HostTables t;
     build_tables(m, t);
     auto up = [&](size_t off, const void *src, size_t bytes) {
@@ -994,15 +1009,31 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
         if ((rc = chfsi_estimate_bounds(c, o->lanczos_steps, v0, &lmax, stream))) return rc;
     }
     if (!(std::isfinite(lmax))) return fail(c, CHFSI_E_BOUNDS, "lambda_max is not finite");
-    hipEvent_t ev[4];
-    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
-    auto cleanup = [&]() { for (auto &e : ev) hipEventDestroy(e); };
+    if (!o->resume) {
+        // a non-finite start block would surface later as a Cholesky breakdown
+        int *flag = c->S<int>(c->L.flag);
+        HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(int), s));
+        HIPCHK(c, launch_check_finite_block(X, 2 * c->m.M, nsub, ld, flag, s));
+        int f = 0;
+        if ((rc = read_flag(c, s, &f))) return rc;
+        if (f) return fail(c, CHFSI_E_NONFINITE, "the start block X holds NaN or Inf");
+    }
+    // timing events, destroyed on every return path
+    struct Events {
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+        ~Events() {
+            for (auto &e : ev)
+                if (e) hipEventDestroy(e);
+        }
+    } evs;
+    hipEvent_t *ev = evs.ev;
+    for (int i = 0; i < 4; ++i) HIPCHK(c, hipEventCreate(&ev[i]));
     HIPCHK(c, hipEventRecord(ev[0], s));
     if (!o->resume) {
-        if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { cleanup(); return rc; }
+        if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) return rc;
         HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));
-        if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) { cleanup(); return rc; }
-        if ((rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s))) { cleanup(); return rc; }
+        if ((rc = orthonormalize_impl(c, X, HX, MX, nsub, ld, s))) return rc;
+        if ((rc = rr_impl(c, X, HX, MX, nsub, ld, ritz, R, res, s))) return rc;
     }
     std::vector<double> hr(nsub), hritz(nsub), titer;
     double t_filter = 0, t_rr = 0, first_res = -1;
@@ -1058,7 +1089,6 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
     HIPCHK(c, hipEventSynchronize(ev[3]));
     float mst = 0;
     hipEventElapsedTime(&mst, ev[0], ev[3]);
-    cleanup();
     HIPCHK(c, hipMemcpy(eigvals, ritz, n_wanted * 8, hipMemcpyDeviceToHost));
     if (rep) {
         rep->iters = it;

@@ -879,7 +879,11 @@ hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int fla
         CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
     }
     if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s);
-    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 4, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
+    // float: 16 vectors per workgroup, except at p = 7 where the two
+    // accumulator sets of 32 column tiles per wave would spill; there 8
+    // vectors per workgroup and two column groups of 16 tiles
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, NP == 512 ? 2 : 4, NP>(c, mode, flags, alpha, X, Y, nvec,
+                                                                                  ld, s)));
 }
 
 // the projection of the bfloat16 path runs in float (complex64 blocks)

@@ -133,6 +133,8 @@ hipError_t launch_cast_block(int64_t rows, int64_t nvec, int64_t ld, const void 
 hipError_t launch_scale_rows(int64_t rows, int64_t nvec, int64_t ld, const double *w, cd *A,
                              hipStream_t s);
 hipError_t launch_check_finite(const double *a, int64_t n, int *flag, hipStream_t s);
+hipError_t launch_check_finite_block(const cd *a, int64_t rows, int64_t nvec, int64_t ld, int *flag,
+                                     hipStream_t s);
 hipError_t launch_dot_real(int64_t n, const cd *a, const cd *b, double *red, double *out,
                            hipStream_t s);
 hipError_t launch_axpby(int64_t n, double a, const cd *x, double b, cd *y, hipStream_t s);

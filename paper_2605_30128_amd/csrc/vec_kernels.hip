@@ -360,6 +360,25 @@ hipError_t launch_check_finite(const double *a, int64_t n, int *flag, hipStream_
     return hipGetLastError();
 }
 
+// the first nvec columns of a complex128 [rows][ld] block (the columns past
+// nvec may hold anything and are not read)
+__global__ void finite_block_kernel(const cd *a, int64_t rows, int64_t nvec, int64_t ld, int *flag) {
+    int bad = 0;
+    const int64_t n = rows * nvec;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / nvec, c = i - r * nvec;
+        const cd v = a[r * ld + c];
+        if (!isfinite(v.x) || !isfinite(v.y)) bad = 1;
+    }
+    if (bad) *flag = 1;
+}
+
+hipError_t launch_check_finite_block(const cd *a, int64_t rows, int64_t nvec, int64_t ld, int *flag,
+                                     hipStream_t s) {
+    hipLaunchKernelGGL(finite_block_kernel, dim3(1024), dim3(256), 0, s, a, rows, nvec, ld, flag);
+    return hipGetLastError();
+}
+
 // out = Re sum conj(a_i) b_i (two stages, fixed order)
 __global__ void dot_partial_kernel(int64_t n, const cd *a, const cd *b, double *red) {
     __shared__ double sm[256];

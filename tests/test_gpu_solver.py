@@ -111,7 +111,10 @@ def test_lanczos_parity(B, tiny_state):
     op = B.Chfsi(s["p"], max_nvec=40)
     v0 = synth.random_block(s["p"].ndof, 1, 402)[:, 0]
     lm = op.estimate_bounds(torch.from_numpy(v0), 20)
-    assert abs(lm - s["lmax"]) < 1e-6 * s["lmax"]
+    # same start vector and FP64 arithmetic: only the summation order of the
+    # products differs, and the extreme Ritz value of 20 steps is stable
+    print("lanczos bound", lm, "oracle", s["lmax"], "rel diff", abs(lm - s["lmax"]) / s["lmax"])
+    assert abs(lm - s["lmax"]) < 1e-10 * s["lmax"]
 
 
 def test_rr_general_parity(B, tiny_state):
