@@ -13,7 +13,7 @@ throughput and the Poisson workload (matrix-free K x throughput with its
 roofline, PCG time to an absolute residual of 1e-10).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16|fp32]
-python bench.py --poisson-only | --hx-only | --converge [--precs fp64,bf16,fp32]
+python bench.py --poisson-only | --slab-only | --hx-only | --converge [--precs fp64,bf16,fp32]
 """
 from __future__ import annotations
 
@@ -44,21 +44,203 @@ def hx_flops(p, nvec):
     return local, nonloc
 
 
-def cpu_baseline(p, nvec=4):
+def _omp():
+    """The OpenMP runtime the oracle library runs on (thread count control)."""
+    import ctypes
+    lib = ctypes.CDLL("libgomp.so.1")
+    lib.omp_get_max_threads.restype = ctypes.c_int
+    return lib
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(p, nvec=4, c0_iters=10):
+    """The oracle timed on the host: H X on the medium mesh with all threads
+    (the reported value) and with one thread, and the C0 (tiny) R-ChFSI
+    solve for c0_iters iterations with all threads."""
     import numpy as np
 
     import oracle
     from paper_2605_30128_amd import synth
     oracle.build(force=False)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    omp = _omp()
+    threads = omp.omp_get_max_threads()
     o = oracle.Oracle(p)
     X = synth.random_block(p.ndof, nvec, 9001)
     t0 = time.perf_counter()
     o.apply_H(X)
     dt = time.perf_counter() - t0
+    omp.omp_set_num_threads(1)
+    t0 = time.perf_counter()
+    o.apply_H(X[:, :1].copy())
+    dt1 = time.perf_counter() - t0
+    omp.omp_set_num_threads(threads)
+    del o, X
+    cfg = synth.CONFIGS["tiny"]
+    pt = synth.make_config("tiny")
+    ot = oracle.Oracle(pt)
+    lmax = ot.lanczos(20, synth.random_block(pt.ndof, 1, 2000)[:, 0])
+    X0 = synth.random_block(pt.ndof, cfg["nsub"], 2001)
+    t0 = time.perf_counter()
+    r = ot.chfsi(X0, cfg["n_wanted"], cfg["cheb_degree"], lmax, tol=0.0, max_iter=c0_iters)
+    dtc = time.perf_counter() - t0
     return {"value": p.ndof * nvec / dt / 1e9, "unit": "GDoF*vec/s", "cores": threads, "kind": "oracle",
-            "sample": f"one H X of {nvec} vectors on the full medium mesh ({p.ndof} dofs), "
-                      f"projector tables included, {dt:.1f} s"}
+            "sample": f"one H X of {nvec} vectors on the full medium mesh ({p.ndof} dofs), projector tables "
+                      f"included, {dt:.1f} s with {threads} threads",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": p.ndof / dt1 / 1e9, "unit": "GDoF*vec/s", "cores": 1,
+                           "sample": f"one H X of 1 vector on the medium mesh, {dt1:.1f} s"},
+            "c0_solve": {"iterations": int(r["iters"]), "seconds": dtc, "sec_per_iter": dtc / max(r["iters"], 1),
+                         "cores": threads,
+                         "sample": f"tiny (C0) R-ChFSI, {cfg['nsub']} columns, degree {cfg['cheb_degree']}, "
+                                   f"{r['iters']} iterations from the seeded start block"}}
+
+
+def c0_gpu(iters=10):
+    """The C0 (tiny) R-ChFSI solve on the GPU in FP64, iters fixed
+    iterations from the same start block as the oracle's C0 timing."""
+    import torch
+
+    from paper_2605_30128_amd import binding, synth
+    cfg = synth.CONFIGS["tiny"]
+    p = synth.make_config("tiny")
+    op = binding.Chfsi(p, max_nvec=cfg["nsub"])
+    X = torch.from_numpy(synth.random_block(p.ndof, cfg["nsub"], 2001)).cuda()
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, 2000)[:, 0])
+    out = op.solve(X, cfg["n_wanted"], cfg["cheb_degree"], prec="fp64", max_iter=iters, fixed_iters=True, v0=v0)
+    return {"iterations": iters, "sec_per_iter_median": out["t_iter_median"], "seconds": out["t_total"],
+            "prec": "fp64"}
+
+
+MID = dict(ncell=(8, 8, 8), box=(12.0, 12.0, 12.0), degree=6, nwells=8, natoms=8, nbeta=8, seed=1010)
+
+
+def gate_leg(precs=("fp64", "fp32", "bf16"), n_wanted=64, nsub=72, degree=30, tol=1e-8):
+    """Mixed precision against FP64 to convergence at a mid-size shape (the
+    medium mesh's cell size and degree on 8^3 cells, 110,592 nodes, 8 atoms
+    x 8 projectors): each precision converges the same start block to the
+    max wanted residual tol, and the wanted eigenvalues are compared with
+    the FP64 run (the 1e-9 Ha gate)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30128_amd import binding, synth
+    p = synth.make_problem(**MID)
+    op = binding.Chfsi(p, max_nvec=nsub)
+    X0 = synth.random_block(p.ndof, nsub, 1011)
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, 1012)[:, 0])
+    res, eig = {}, {}
+    for prec in precs:
+        X = torch.from_numpy(X0).cuda()
+        r = op.solve(X, n_wanted, degree, prec=prec, tol=tol, max_iter=300, v0=v0, rr_mode=2)
+        eig[prec] = r["eigvals"]
+        res[prec] = {"iterations": r["iters"], "converged": r["converged"], "max_res": r["max_res"],
+                     "sec_per_iter_median": r["t_iter_median"], "seconds": r["t_total"]}
+        if prec != "fp64" and "fp64" in eig:
+            res[prec]["max_abs_eig_diff_vs_fp64"] = float(np.abs(r["eigvals"] - eig["fp64"]).max())
+        log(f"[bench] gate {prec}: {r['iters']} iterations to {r['max_res']:.2e}, "
+            f"{r['t_iter_median'] * 1e3:.1f} ms/iter" +
+            (f", max |dlambda| vs fp64 {res[prec]['max_abs_eig_diff_vs_fp64']:.2e} Ha"
+             if "max_abs_eig_diff_vs_fp64" in res[prec] else ""))
+    del op
+    torch.cuda.empty_cache()
+    return {"shape": f"8x8x8 cells of 1.5 bohr, p=6, {p.nnodes} nodes, {p.natoms} atoms x {p.nbeta} projectors, "
+                     f"{n_wanted} wanted in {nsub} columns, Chebyshev degree {degree}, tol {tol:g}",
+            "gate_ha": 1e-9, **res}
+
+
+def cell_roofline(p, prec, nvec, ms_cell, launches, config):
+    """Roofline of the cell-operator kernel: algorithmic flops (local plus the
+    apply half of the spin-orbit term) and bytes (read X, write Y once) per
+    launch over the device-event launch time."""
+    loc, nl = hx_flops(p, nvec)
+    flops_launch = (loc + nl / 2) / launches  # the projection half runs in the coefficient kernels
+    bytes_launch = 2 * p.ndof * nvec * CSIZE[prec] / launches
+    t_launch = ms_cell * 1e-3 / launches
+    if flops_launch / PEAK[prec] >= bytes_launch / PEAK["hbm"]:
+        roof = {"bound": "mfma", "achieved": flops_launch / t_launch / 1e12, "peak": PEAK[prec] / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_launch / t_launch / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(prec, config, nvec)
+    roof["kernel"] = f"cell_kernel ({prec}), avg of {launches} colour launches per H X, {nvec} vectors"
+    roof["flops_per_launch"] = flops_launch
+    roof["bytes_per_launch"] = bytes_launch
+    roof["ms_per_launch"] = t_launch * 1e3
+    return roof
+
+
+def slab_leg(nvec=256, degree=40, reps=3):
+    """The largest one-GPU share (periodic slab, 32 x 32 x 24 cells, p = 7,
+    8,429,568 nodes, 256 atoms x 8 projectors), one block of nvec vectors:
+    H X in FP64, FP32 and bfloat16 with the cell kernel's roofline, and the
+    degree-40 filter pass over one block of wavefunctions in bfloat16
+    (nvec columns) and FP64 (nvec/2 columns, the widest FP64 block beside
+    the other buffers in 288 GB) on synthetic X, R and Ritz values."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30128_amd import binding, synth
+    t0 = time.perf_counter()
+    p = synth.make_config("slab")
+    log(f"[bench] slab generated: {p.ndof} dofs, {p.npairs} pairs in {time.perf_counter() - t0:.0f}s")
+    op = binding.Chfsi(p, max_nvec=nvec, filter_block=nvec, filter_prec="bf16")
+    out = {"nodes": p.nnodes, "dofs": p.ndof, "cells": p.ncells, "degree": p.degree, "vectors": nvec,
+           "hx_gdofvec_per_s": {}, "hx_profile_ms": {}, "roofline": {}}
+    X = synth.device_block(p.ndof, nvec, 801)
+    for prec in ("fp64", "fp32", "bf16"):
+        if prec != "fp64" and X.dtype == torch.complex128:
+            X = X.to(torch.complex64)
+            torch.cuda.empty_cache()
+        Y = torch.empty_like(X)
+        op.apply_H(X, prec=prec, Y=Y)
+        r = [op.profile_apply_H(X, prec=prec, Y=Y) for _ in range(reps)]
+        cell, coef, tot = (float(np.median([v[i] for v in r])) for i in range(3))
+        out["hx_gdofvec_per_s"][prec] = p.ndof * nvec / (tot * 1e-3) / 1e9
+        out["hx_profile_ms"][prec] = dict(ms_cell=cell, ms_coeff=coef, ms_total=tot, launches=r[0][3])
+        out["roofline"][prec] = cell_roofline(p, prec, nvec, cell, r[0][3], "slab")
+        log(f"[bench] slab H X {prec}: {tot:.1f} ms ({cell:.1f} cell) -> {out['hx_gdofvec_per_s'][prec]:.2f} "
+            f"GDoF*vec/s, {out['roofline'][prec]['frac']:.3f} of the {out['roofline'][prec]['bound']} roof")
+        del Y
+    del X
+    torch.cuda.empty_cache()
+    v0 = synth.device_block(p.ndof, 1, 802)[:, 0].contiguous()
+    lmax = op.estimate_bounds(v0, 20)
+    del v0
+    Xf = synth.device_block(p.ndof, nvec, 803)
+    R = synth.device_block(p.ndof, nvec, 804)
+    R.mul_(1e-3)
+    ritz = torch.linspace(-1.0, 2.0, nvec, dtype=torch.float64)
+    bounds = [-1.0, 2.0, lmax]
+    filt = {}
+    for prec, ncol in (("bf16", nvec), ("fp64", nvec // 2)):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        op.filter(Xf, ritz, R, degree, bounds, prec=prec, Y=Xf, nvec=ncol)
+        ev[1].record()
+        torch.cuda.synchronize()
+        sec = ev[0].elapsed_time(ev[1]) * 1e-3
+        filt[prec] = {"columns": ncol, "seconds": sec, "sec_per_column": sec / ncol,
+                      "hx_gdofvec_per_s": (degree - 1) * p.ndof * ncol / sec / 1e9}
+        log(f"[bench] slab filter {prec}: degree {degree}, {ncol} columns in {sec:.2f} s "
+            f"({filt[prec]['hx_gdofvec_per_s']:.2f} GDoF*vec/s of H X)")
+    filt["bf16_speedup_per_column"] = filt["fp64"]["sec_per_column"] / filt["bf16"]["sec_per_column"]
+    filt["lambda_max"] = lmax
+    out["filter_degree40"] = filt
+    del Xf, R, op
+    torch.cuda.empty_cache()
+    return out
 
 
 def bfp_throughput(n=1 << 28, reps=5):
@@ -307,6 +489,9 @@ def main():
                          "calibrate the memory counters")
     ap.add_argument("--hx-precs", default="fp64,fp32,bf16")
     ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson (K x, PCG) leg")
+    ap.add_argument("--no-gate", action="store_true", help="skip the mid-size mixed-vs-FP64 convergence leg")
+    ap.add_argument("--no-slab", action="store_true", help="skip the largest-share (slab) leg")
+    ap.add_argument("--slab-only", action="store_true", help="run only the slab leg")
     ap.add_argument("--poisson-only", action="store_true", help="run only the Poisson leg")
     ap.add_argument("--no-pcg", action="store_true", help="Poisson leg: K x only")
     ap.add_argument("--kx-reps", type=int, default=50)
@@ -338,6 +523,9 @@ def main():
         if not args.no_cpu_baseline:
             poi["cpu_baseline"] = cpu_poisson_baseline()
         print(json.dumps({"poisson": poi}), flush=True)
+        return
+    if args.slab_only:
+        print(json.dumps({"slab": slab_leg()}), flush=True)
         return
     cfg = synth.CONFIGS[args.config]
     t0 = time.perf_counter()
@@ -411,28 +599,21 @@ def main():
         torch.cuda.synchronize()
         it64 = time.perf_counter() - t1
         log(f"[bench] 1 fp64 iteration: {it64 * 1e3:.1f} ms (filter {o64['t_filter']:.3f}s)")
+    it32 = None
+    if not args.no_fp64_iter and args.prec != "fp32":
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o32 = op.solve(X, n_wanted, q, prec="fp32", max_iter=1, fixed_iters=True, resume=True, work=work,
+                       lambda_max=lmax, rr_mode=args.rr_mode)
+        torch.cuda.synchronize()
+        it32 = time.perf_counter() - t1
+        log(f"[bench] 1 fp32 iteration: {it32 * 1e3:.1f} ms (filter {o32['t_filter']:.3f}s)")
+    del X, work, out
+    torch.cuda.empty_cache()
 
     # ---- roofline of the dominant kernel: the cell operator in the step's precision
     pr = args.prec
-    loc, nl = hx_flops(p, nhx)
-    launches = prof[pr]["launches"]
-    flops_launch = (loc + nl / 2) / launches  # the projection half runs in the coefficient kernels
-    bytes_launch = 2 * p.ndof * nhx * CSIZE[pr] / launches  # read X once, write Y once
-    t_launch = prof[pr]["ms_cell"] * 1e-3 / launches
-    t_flop = flops_launch / PEAK[pr]
-    t_byte = bytes_launch / PEAK["hbm"]
-    if t_flop >= t_byte:
-        roof = {"bound": "mfma", "achieved": flops_launch / t_launch / 1e12, "peak": PEAK[pr] / 1e12,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": bytes_launch / t_launch / 1e9, "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(pr, args.config, nhx)
-    roof["kernel"] = f"cell_kernel ({pr}), avg of {launches} colour launches per H X, {nhx} vectors"
-    roof["flops_per_launch"] = flops_launch
-    roof["bytes_per_launch"] = bytes_launch
-    roof["ms_per_launch"] = t_launch * 1e3
+    roof = cell_roofline(p, pr, nhx, prof[pr]["ms_cell"], prof[pr]["launches"], args.config)
 
     bfp = bfp_throughput()
     log(f"[bench] bfp codec: " + ", ".join(f"{k} enc {v['encode_GBps']:.0f} / dec {v['decode_GBps']:.0f} GB/s"
@@ -447,10 +628,16 @@ def main():
             except Exception as e:  # the baseline is a report, never the product
                 log(f"[bench] cpu poisson baseline failed: {e}")
 
+    del op
+    torch.cuda.empty_cache()
+    gate = None if args.no_gate else gate_leg()
+    slab = None if args.no_slab else slab_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         try:
             cpu = cpu_baseline(p)
+            cpu["c0_gpu"] = c0_gpu()
             log(f"[bench] cpu baseline: {cpu}")
         except Exception as e:  # the baseline is a report, never the product
             log(f"[bench] cpu baseline failed: {e}")
@@ -477,7 +664,9 @@ def main():
             "hx_vectors": nhx,
             "nsub": nsub,
         },
-        "sec_per_iter": {pr: ms_step / 1e3, "fp64": it64},
+        "sec_per_iter": {pr: ms_step / 1e3, "fp64": it64, **({"fp32": it32} if it32 is not None else {})},
+        "mixed_vs_fp64_gate": gate,
+        "slab": slab,
         "hx_gdofvec_per_s": hx,
         "hx_profile_ms": prof,
         "roofline": roof,

@@ -106,10 +106,33 @@ typedef struct {
 
 /* Sizes of the caller-allocated buffers for blocks of up to max_nvec
  * vectors.  persistent: operator tables (all precisions); scratch:
- * temporaries of apply, filter (three recurrence blocks) and Rayleigh-Ritz.
- * Both must be 256-byte aligned device memory. */
+ * temporaries of apply, filter (two recurrence blocks of max_nvec complex128
+ * columns) and Rayleigh-Ritz.  Both must be 256-byte aligned device memory.
+ * Same as chfsi_plan_ex with {max_nvec, 0, CHFSI_FP64}. */
 int chfsi_plan(const chfsi_mesh *mesh, const chfsi_projectors *proj, int64_t max_nvec,
                size_t *persistent_bytes, size_t *scratch_bytes);
+
+/* Scratch sizing for filtering in blocks of wavefunctions (Sec. III-C4: the
+ * subspace is processed in column blocks) and for the narrower recurrence
+ * blocks of the reduced-precision filters (Sec. III-C2: Z in FP32). */
+typedef struct {
+    int64_t max_nvec;       /* largest block of any call (the subspace N_s) */
+    int64_t filter_block;   /* largest column count of one filter pass
+                               (chfsi_filter nvec, chfsi_solve_opts.block);
+                               0 means max_nvec; <= max_nvec */
+    chfsi_prec filter_prec; /* widest filter precision at filter_block columns:
+                               CHFSI_FP64 sizes complex128 recurrence blocks,
+                               CHFSI_FP32 / CHFSI_BF16 complex64 (half the
+                               bytes; an FP64 filter then fits only half as
+                               many columns and reports CHFSI_E_WORKSPACE
+                               beyond that) */
+} chfsi_plan_opts;
+
+/* Buffer sizes for the options above.  The recurrence area also serves the
+ * Rayleigh-Ritz rotations and Gram partials, which run in row chunks when it
+ * is smaller than a complex128 block of max_nvec columns. */
+int chfsi_plan_ex(const chfsi_mesh *mesh, const chfsi_projectors *proj, const chfsi_plan_opts *opts,
+                  size_t *persistent_bytes, size_t *scratch_bytes);
 
 /* Builds the operator tables (Sec. III-A quadrature; Sec. III-C2 cell
  * matrices) into `persistent` and returns a context.  V, B: device fields
@@ -120,6 +143,12 @@ int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B,
                 const chfsi_projectors *proj, int64_t max_nvec,
                 void *persistent, size_t persistent_bytes,
                 void *scratch, size_t scratch_bytes, void *stream, chfsi_ctx **out);
+
+/* chfsi_setup with the buffers sized by chfsi_plan_ex for the same opts. */
+int chfsi_setup_ex(const chfsi_mesh *mesh, const double *V, const double *B,
+                   const chfsi_projectors *proj, const chfsi_plan_opts *opts,
+                   void *persistent, size_t persistent_bytes,
+                   void *scratch, size_t scratch_bytes, void *stream, chfsi_ctx **out);
 
 /* Replaces the fields V, B (device) of an existing context (same mesh).
  * Synchronizes; CHFSI_E_NONFINITE if V or B holds NaN or Inf, in which case
@@ -162,7 +191,9 @@ int chfsi_estimate_bounds(chfsi_ctx *ctx, int lanczos_steps, const void *v0,
  * Lambda_k = C_k(diag(ritz)) by the same three-term rule.  The products
  * H D^{-1} Z_k run in `prec` (Z stored in its complex type); X, R, Y are
  * complex128 and R Lambda_k is formed in double.  ritz: double device [nvec].
- * Y may alias X. */
+ * Y may alias X.  The two recurrence blocks live in the scratch buffer:
+ * CHFSI_E_WORKSPACE if nvec columns of the precision's complex type exceed
+ * what chfsi_plan_ex sized (filter_block, filter_prec). */
 int chfsi_filter(chfsi_ctx *ctx, chfsi_prec prec, int degree, const double bounds[3],
                  const void *X, const double *ritz, const void *R, void *Y,
                  int64_t nvec, int64_t ld, void *stream);
@@ -222,6 +253,10 @@ typedef struct {
                            (Ritz vectors, HX, MX, R, Ritz values): the initial
                            orthonormalization, Rayleigh-Ritz and the Lanczos
                            bound are skipped and lambda_max is taken from opts */
+    int64_t block;      /* columns per filter pass (blocks of wavefunctions,
+                           Sec. III-C4); 0: min(nsub, filter_block).  The
+                           filter is column-wise, so blocking changes no
+                           result */
 } chfsi_solve_opts;
 
 typedef struct {

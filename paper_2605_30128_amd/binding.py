@@ -43,7 +43,11 @@ class _Proj(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("prec", C.c_int), ("degree", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("lanczos_steps", C.c_int), ("lambda_max", C.c_double), ("fixed_iters", C.c_int),
-                ("rr_mode", C.c_int), ("resume", C.c_int)]
+                ("rr_mode", C.c_int), ("resume", C.c_int), ("block", C.c_int64)]
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("max_nvec", C.c_int64), ("filter_block", C.c_int64), ("filter_prec", C.c_int)]
 
 
 class Report(C.Structure):
@@ -64,7 +68,7 @@ class PcgReport(C.Structure):
 
 
 SYMBOLS = [
-    "chfsi_plan", "chfsi_setup", "chfsi_set_fields", "chfsi_apply_H", "chfsi_apply_M",
+    "chfsi_plan", "chfsi_setup", "chfsi_plan_ex", "chfsi_setup_ex", "chfsi_set_fields", "chfsi_apply_H", "chfsi_apply_M",
     "chfsi_apply_H_adjoint", "chfsi_estimate_bounds", "chfsi_filter", "chfsi_orthonormalize",
     "chfsi_rayleigh_ritz", "chfsi_rayleigh_ritz_general", "chfsi_residual", "chfsi_solve_workspace", "chfsi_solve", "chfsi_info",
     "chfsi_mass_diag", "chfsi_profile_apply_H", "chfsi_bfp_bytes", "chfsi_bfp_encode", "chfsi_bfp_decode",
@@ -86,6 +90,8 @@ def load(path: str = LIB_PATH):
     vp, i64, i = C.c_void_p, C.c_int64, C.c_int
     L.chfsi_plan.argtypes = [vp, vp, i64, vp, vp]
     L.chfsi_setup.argtypes = [vp, vp, vp, vp, i64, vp, C.c_size_t, vp, C.c_size_t, vp, vp]
+    L.chfsi_plan_ex.argtypes = [vp, vp, vp, vp, vp]
+    L.chfsi_setup_ex.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, vp, C.c_size_t, vp, vp]
     L.chfsi_set_fields.argtypes = [vp, vp, vp, vp]
     L.chfsi_apply_H.argtypes = [vp, i, vp, vp, i64, i64, vp]
     L.chfsi_apply_M.argtypes = [vp, vp, vp, i64, i64, vp]
@@ -181,11 +187,15 @@ class ProblemArrays:
 class Chfsi:
     """One operator (mesh, fields, projectors) on the current CUDA device."""
 
-    def __init__(self, prob, max_nvec: int, device="cuda"):
+    def __init__(self, prob, max_nvec: int, device="cuda", filter_block: int = 0, filter_prec="fp64"):
+        """filter_block, filter_prec: scratch sizing of the filter's two
+        recurrence blocks (chfsi_plan_ex); the defaults hold max_nvec
+        complex128 columns."""
         L = load()
         self.L = L
         self.prob = prob
         self.max_nvec = int(max_nvec)
+        self._popts = PlanOpts(self.max_nvec, int(filter_block), PREC[filter_prec])
         self.device = torch.device(device)
         self._mesh = _Mesh((C.c_int64 * 3)(*prob.ncell), (C.c_double * 3)(*prob.h), int(prob.degree),
                            int(prob.nq1))
@@ -198,16 +208,16 @@ class Chfsi:
         self._proj = _Proj(natoms, int(prob.nbeta), k[0].ctypes.data, k[1].ctypes.data,
                            k[2].ctypes.data, k[3].ctypes.data)
         pb, sb = C.c_size_t(), C.c_size_t()
-        self._check(L.chfsi_plan(C.byref(self._mesh), C.byref(self._proj), self.max_nvec,
-                                 C.byref(pb), C.byref(sb)), None)
+        self._check(L.chfsi_plan_ex(C.byref(self._mesh), C.byref(self._proj), C.byref(self._popts),
+                                    C.byref(pb), C.byref(sb)), None)
         self.persistent = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
         self.scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
         self.V = torch.as_tensor(np.ascontiguousarray(prob.V, np.float64), device=self.device)
         self.B = torch.as_tensor(np.ascontiguousarray(prob.B, np.float64), device=self.device)
         ctx = C.c_void_p()
-        self._check(L.chfsi_setup(C.byref(self._mesh), _ptr(self.V), _ptr(self.B), C.byref(self._proj),
-                                  self.max_nvec, _ptr(self.persistent), pb.value, _ptr(self.scratch),
-                                  sb.value, _stream(), C.byref(ctx)), None)
+        self._check(L.chfsi_setup_ex(C.byref(self._mesh), _ptr(self.V), _ptr(self.B), C.byref(self._proj),
+                                     C.byref(self._popts), _ptr(self.persistent), pb.value, _ptr(self.scratch),
+                                     sb.value, _stream(), C.byref(ctx)), None)
         self.ctx = ctx
         nn, nc, n, nq = C.c_int64(), C.c_int64(), C.c_int(), C.c_int()
         L.chfsi_info(ctx, C.byref(nn), C.byref(nc), C.byref(n), C.byref(nq))
@@ -367,7 +377,8 @@ class Chfsi:
         return ms[0], ms[1], ms[2], nl.value
 
     def solve(self, X, n_wanted, degree, prec="fp64", tol=1e-8, max_iter=100, v0=None,
-              lanczos_steps=20, lambda_max=0.0, fixed_iters=False, resume=False, work=None, rr_mode=1):
+              lanczos_steps=20, lambda_max=0.0, fixed_iters=False, resume=False, work=None, rr_mode=1,
+              block=0):
         """Algorithm RChFSI from the start block X (overwritten with Ritz vectors).
         resume=True continues from the state a previous call left in X and
         `work` (returned as out['work']); lambda_max must then be given."""
@@ -381,7 +392,7 @@ class Chfsi:
             work = torch.empty(ws.value, dtype=torch.uint8, device=X.device)
         opts = SolveOpts(PREC[prec], int(degree), float(tol), int(max_iter),
                          int(lanczos_steps if v0 is not None else 0), float(lambda_max), int(fixed_iters),
-                         int(rr_mode), int(resume))
+                         int(rr_mode), int(resume), int(block))
         eig = np.zeros(n_wanted)
         hist = np.zeros(max_iter + 2)
         rep = Report()

@@ -183,7 +183,12 @@ int build_mesh(const chfsi_mesh *mesh, const chfsi_projectors *proj, Mesh &m, st
     return CHFSI_OK;
 }
 
-Layout build_layout(const Mesh &m, int64_t max_nvec) {
+// Bytes of one recurrence block of nvec columns in the filter's complex type.
+size_t zblock_bytes(const Mesh &m, int64_t nvec, bool z32) {
+    return align256((size_t)(2 * m.M) * nvec * (z32 ? sizeof(cf) : sizeof(cd)));
+}
+
+Layout build_layout(const Mesh &m, int64_t max_nvec, int64_t filter_block, chfsi_prec filter_prec) {
     Layout L{};
     size_t o = 0;
     const size_t NP2 = (size_t)m.npad * m.npad;
@@ -224,10 +229,15 @@ Layout build_layout(const Mesh &m, int64_t max_nvec) {
     L.red_bytes = (size_t)256 * std::max<int64_t>(max_nvec, 2) * 8 + 4096 * 8;
     L.red = take(L.red_bytes);
     L.flag = take(256);
-    // filter: three recurrence blocks; Lanczos: four vectors and a table of M
-    L.Z = take(std::max<size_t>(3 * (size_t)(2 * m.M) * max_nvec * 16, 5 * (size_t)(2 * m.M) * 16));
+    // filter: two recurrence blocks (Z_{k+1} overwrites Z_{k-1} element by
+    // element); Lanczos: four vectors and a table of M.  The Rayleigh-Ritz
+    // rotations and the split-K Gram partials use the same area in row chunks.
+    L.zarea = std::max<size_t>(2 * zblock_bytes(m, filter_block, filter_prec != CHFSI_FP64),
+                               5 * (size_t)(2 * m.M) * 16);
+    L.Z = take(L.zarea);
     size_t phi_bytes = (size_t)m.npairs * m.nq * 2 * m.nbeta * 16;
     L.scratch_bytes = std::max(o, align256(L.Z + phi_bytes));
+    L.zarea = L.scratch_bytes - L.Z;
     return L;
 }
 
@@ -433,7 +443,7 @@ int gram(chfsi_ctx *c, const cd *A, const cd *B, int64_t N, int64_t ld, cd *Sm, 
     BLASCHK(c, rocblas_set_stream(c->blas, s));
     const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
     const int64_t rows = 2 * c->m.M;
-    const size_t zcap = (c->L.scratch_bytes - c->L.Z) / sizeof(cd);
+    const size_t zcap = c->L.zarea / sizeof(cd);
     int64_t nb = 128;
     while (nb > 1 && ((size_t)(nb + 1) * N * N > zcap || rows / nb < 4096)) nb /= 2;
     auto rb = [](const cd *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
@@ -479,18 +489,29 @@ int small_mm(chfsi_ctx *c, const cd *A, const cd *B, cd *Cm, int64_t N, bool con
 
 // A <- A Q (A: [rows][ld] block with N columns; Q: N x N row-major), through
 // the compact temporary Z buffer and a strided copy back.
+// Rows of a block whose temporaries (bytes_per_row each) fit the Z area at
+// once: the whole block when the scratch was planned for it, else chunks.
+int64_t row_chunk(const chfsi_ctx *c, size_t bytes_per_row) {
+    const int64_t rows = 2 * c->m.M;
+    const int64_t cap = (int64_t)(c->L.zarea / bytes_per_row);
+    return std::max<int64_t>(1, std::min(rows, cap));
+}
+
 int rotate(chfsi_ctx *c, cd *A, const cd *Q, int64_t N, int64_t ld, hipStream_t s) {
     cd *tmp = c->S<cd>(c->L.Z);
-    const int64_t rows = 2 * c->m.M;
+    const int64_t rows = 2 * c->m.M, rc = row_chunk(c, (size_t)N * sizeof(cd));
     BLASCHK(c, rocblas_set_stream(c->blas, s));
     const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
-    BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N,
-                             (rocblas_int)rows, (rocblas_int)N, &one,
-                             reinterpret_cast<const rocblas_double_complex *>(Q), (rocblas_int)N,
-                             reinterpret_cast<const rocblas_double_complex *>(A), (rocblas_int)ld, &zero,
-                             reinterpret_cast<rocblas_double_complex *>(tmp), (rocblas_int)N));
-    HIPCHK(c, hipMemcpy2DAsync(A, ld * sizeof(cd), tmp, N * sizeof(cd), N * sizeof(cd), rows,
-                               hipMemcpyDeviceToDevice, s));
+    for (int64_t r0 = 0; r0 < rows; r0 += rc) {
+        const int64_t nr = std::min(rc, rows - r0);
+        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N,
+                                 (rocblas_int)nr, (rocblas_int)N, &one,
+                                 reinterpret_cast<const rocblas_double_complex *>(Q), (rocblas_int)N,
+                                 reinterpret_cast<const rocblas_double_complex *>(A + r0 * ld), (rocblas_int)ld,
+                                 &zero, reinterpret_cast<rocblas_double_complex *>(tmp), (rocblas_int)N));
+        HIPCHK(c, hipMemcpy2DAsync(A + r0 * ld, ld * sizeof(cd), tmp, N * sizeof(cd), N * sizeof(cd), nr,
+                                   hipMemcpyDeviceToDevice, s));
+    }
     return CHFSI_OK;
 }
 
@@ -501,34 +522,39 @@ int rotate(chfsi_ctx *c, cd *A, const cd *Q, int64_t N, int64_t ld, hipStream_t 
 // FP64.  Q32 is scratch for an N x N complex64 matrix.
 constexpr int64_t SRB = 64;
 int rotate_mixed(chfsi_ctx *c, cd *A, const cd *Q, int64_t N, int64_t ld, cf *Q32, hipStream_t s) {
-    const int64_t rows = 2 * c->m.M;
+    const int64_t rows = 2 * c->m.M, rc = row_chunk(c, (size_t)N * (sizeof(cd) + 2 * sizeof(cf)));
     cd *T = c->S<cd>(c->L.Z);
-    cf *A32 = reinterpret_cast<cf *>(T + rows * N), *C32 = A32 + rows * N;
+    cf *A32 = reinterpret_cast<cf *>(T + rc * N), *C32 = A32 + rc * N;
     BLASCHK(c, rocblas_set_stream(c->blas, s));
     const rocblas_double_complex one{1.0, 0.0}, zero{0.0, 0.0};
     const rocblas_float_complex onef{1.0f, 0.0f}, zerof{0.0f, 0.0f};
     auto zc = [](const cd *p) { return reinterpret_cast<const rocblas_double_complex *>(p); };
     const int64_t nfull = N / SRB, rem = N - nfull * SRB;
-    if (nfull > 0)
-        BLASCHK(c, rocblas_zgemm_strided_batched(
-                       c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)SRB, (rocblas_int)rows,
-                       (rocblas_int)SRB, &one, zc(Q), (rocblas_int)N, (rocblas_stride)(SRB * (N + 1)), zc(A),
-                       (rocblas_int)ld, (rocblas_stride)SRB, &zero, reinterpret_cast<rocblas_double_complex *>(T),
-                       (rocblas_int)N, (rocblas_stride)SRB, (rocblas_int)nfull));
-    if (rem > 0) {
-        const int64_t o = nfull * SRB;
-        BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)rem,
-                                 (rocblas_int)rows, (rocblas_int)rem, &one, zc(Q + o * N + o), (rocblas_int)N,
-                                 zc(A + o), (rocblas_int)ld, &zero, reinterpret_cast<rocblas_double_complex *>(T + o),
-                                 (rocblas_int)N));
-    }
     HIPCHK(c, launch_offdiag_cf((int)N, (int)SRB, Q, Q32, s));
-    HIPCHK(c, launch_sr_to_cf(rows, N, ld, A, A32, s));
-    BLASCHK(c, rocblas_cgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N, (rocblas_int)rows,
-                             (rocblas_int)N, &onef, reinterpret_cast<const rocblas_float_complex *>(Q32), (rocblas_int)N,
-                             reinterpret_cast<const rocblas_float_complex *>(A32), (rocblas_int)N, &zerof,
-                             reinterpret_cast<rocblas_float_complex *>(C32), (rocblas_int)N));
-    HIPCHK(c, launch_sr_combine(rows, N, ld, T, C32, A, s));
+    for (int64_t r0 = 0; r0 < rows; r0 += rc) {
+        const int64_t nr = std::min(rc, rows - r0);
+        cd *Ar = A + r0 * ld;
+        if (nfull > 0)
+            BLASCHK(c, rocblas_zgemm_strided_batched(
+                           c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)SRB, (rocblas_int)nr,
+                           (rocblas_int)SRB, &one, zc(Q), (rocblas_int)N, (rocblas_stride)(SRB * (N + 1)), zc(Ar),
+                           (rocblas_int)ld, (rocblas_stride)SRB, &zero, reinterpret_cast<rocblas_double_complex *>(T),
+                           (rocblas_int)N, (rocblas_stride)SRB, (rocblas_int)nfull));
+        if (rem > 0) {
+            const int64_t o = nfull * SRB;
+            BLASCHK(c, rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)rem,
+                                     (rocblas_int)nr, (rocblas_int)rem, &one, zc(Q + o * N + o), (rocblas_int)N,
+                                     zc(Ar + o), (rocblas_int)ld, &zero,
+                                     reinterpret_cast<rocblas_double_complex *>(T + o), (rocblas_int)N));
+        }
+        HIPCHK(c, launch_sr_to_cf(nr, N, ld, Ar, A32, s));
+        BLASCHK(c, rocblas_cgemm(c->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)N,
+                                 (rocblas_int)nr, (rocblas_int)N, &onef,
+                                 reinterpret_cast<const rocblas_float_complex *>(Q32), (rocblas_int)N,
+                                 reinterpret_cast<const rocblas_float_complex *>(A32), (rocblas_int)N, &zerof,
+                                 reinterpret_cast<rocblas_float_complex *>(C32), (rocblas_int)N));
+        HIPCHK(c, launch_sr_combine(nr, N, ld, T, C32, Ar, s));
+    }
     return CHFSI_OK;
 }
 
@@ -650,11 +676,18 @@ int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds,
     const double cc = 0.5 * (lmax + lT), e = 0.5 * (lmax - lT);
     const double s1 = e / (lmin - cc);
     const bool z32 = prec != CHFSI_FP64;
-    const size_t zsz = z32 ? sizeof(cf) : sizeof(cd);
     const int64_t rows = 2 * c->m.M;
     char *zb = c->scr + L.Z;
-    const size_t zstride = align256((size_t)rows * nvec * zsz);
-    void *Zp = zb, *Zc = zb + zstride, *Zn = zb + 2 * zstride;
+    const size_t zstride = zblock_bytes(c->m, nvec, z32);
+    if (2 * zstride > L.zarea)
+        return fail(c, CHFSI_E_WORKSPACE, "the scratch holds two recurrence blocks of " +
+                                              std::to_string(L.zarea / 2) + " bytes; this filter needs " +
+                                              std::to_string(zstride) + " (plan a larger filter_block or a "
+                                              "narrower filter precision)");
+    // two blocks: Z_k is read by the products, Z_{k+1} is written over
+    // Z_{k-1} element by element (each element of Z_{k-1} is read only by
+    // the update that overwrites it)
+    void *Zc = zb, *Zn = zb + zstride, *Zp = nullptr;
     double *lamk = c->S<double>(L.lamk);
     HIPCHK(c, launch_lamk_table(ritz, nvec, degree, cc, e, s1, lamk, nvec, s));
     // Z_1 = s1 R / e
@@ -667,12 +700,14 @@ int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds,
         const double sn = 1.0 / (2.0 / s1 - sk);
         const double a = 2.0 * sn / e;
         // Z_{k+1} = -a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k
-        HIPCHK(c, launch_filter_init_ld(rows, nvec, nvec, ld, z32, Zn, Zc, k > 1 ? Zp : nullptr, R, -a * cc,
-                                        -sk * sn, lamk + (int64_t)k * nvec, a, s));
+        if (Zp) Zn = Zp;  // Z_{k+1} over Z_{k-1}
+        HIPCHK(c, launch_filter_init_ld(rows, nvec, nvec, ld, z32, Zn, Zc, Zp, R, -a * cc, -sk * sn,
+                                        lamk + (int64_t)k * nvec, a, s));
         // Z_{k+1} += a H D^{-1} Z_k
         if (nl) HIPCHK(c, launch_nonlocal_coeffs(c, prec, FLAG_DINV, Zc, nvec, nvec, s));
         HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_ACCUM | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s));
-        void *t = Zp; Zp = Zc; Zc = Zn; Zn = t;
+        Zp = Zc;
+        Zc = Zn;
         sk = sn;
     }
     HIPCHK(c, launch_recover_ld(rows, nvec, nvec, ld, z32, Zc, c->P<double>(L.Dinv64), X,
@@ -685,32 +720,60 @@ int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds,
 // =========================================================================
 extern "C" {
 
-int chfsi_plan(const chfsi_mesh *mesh, const chfsi_projectors *proj, int64_t max_nvec,
-               size_t *persistent_bytes, size_t *scratch_bytes) {
+static int plan_opts_check(const chfsi_plan_opts *po, int64_t &max_nvec, int64_t &fblock, chfsi_prec &fprec) {
+    if (!po) return fail(nullptr, CHFSI_E_ARG, "plan options are NULL");
+    max_nvec = po->max_nvec;
+    fblock = po->filter_block > 0 ? po->filter_block : po->max_nvec;
+    fprec = po->filter_prec;
+    if (max_nvec < 1) return fail(nullptr, CHFSI_E_ARG, "max_nvec must be >= 1");
+    if (fblock > max_nvec) return fail(nullptr, CHFSI_E_ARG, "filter_block must be <= max_nvec");
+    if (fprec < CHFSI_FP64 || fprec > CHFSI_BF16) return fail(nullptr, CHFSI_E_ARG, "unknown filter precision");
+    return CHFSI_OK;
+}
+
+int chfsi_plan_ex(const chfsi_mesh *mesh, const chfsi_projectors *proj, const chfsi_plan_opts *po,
+                  size_t *persistent_bytes, size_t *scratch_bytes) {
     Mesh m{};
     std::string msg;
     int rc = build_mesh(mesh, proj, m, msg);
     if (rc) return fail(nullptr, rc, msg);
-    if (max_nvec < 1) return fail(nullptr, CHFSI_E_ARG, "max_nvec must be >= 1");
+    int64_t max_nvec, fblock;
+    chfsi_prec fprec;
+    if ((rc = plan_opts_check(po, max_nvec, fblock, fprec))) return rc;
     if (!persistent_bytes || !scratch_bytes) return fail(nullptr, CHFSI_E_ARG, "size outputs are NULL");
-    Layout L = build_layout(m, max_nvec);
+    Layout L = build_layout(m, max_nvec, fblock, fprec);
     *persistent_bytes = L.persistent_bytes;
     *scratch_bytes = L.scratch_bytes;
     return CHFSI_OK;
 }
 
+int chfsi_plan(const chfsi_mesh *mesh, const chfsi_projectors *proj, int64_t max_nvec,
+               size_t *persistent_bytes, size_t *scratch_bytes) {
+    const chfsi_plan_opts po{max_nvec, 0, CHFSI_FP64};
+    return chfsi_plan_ex(mesh, proj, &po, persistent_bytes, scratch_bytes);
+}
+
 int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B, const chfsi_projectors *proj,
                 int64_t max_nvec, void *persistent, size_t persistent_bytes, void *scratch,
                 size_t scratch_bytes, void *stream, chfsi_ctx **out) {
+    const chfsi_plan_opts po{max_nvec, 0, CHFSI_FP64};
+    return chfsi_setup_ex(mesh, V, B, proj, &po, persistent, persistent_bytes, scratch, scratch_bytes, stream, out);
+}
+
+int chfsi_setup_ex(const chfsi_mesh *mesh, const double *V, const double *B, const chfsi_projectors *proj,
+                   const chfsi_plan_opts *po, void *persistent, size_t persistent_bytes, void *scratch,
+                   size_t scratch_bytes, void *stream, chfsi_ctx **out) {
     if (!out) return fail(nullptr, CHFSI_E_ARG, "out is NULL");
     *out = nullptr;
     Mesh m{};
     std::string msg;
     int rc = build_mesh(mesh, proj, m, msg);
     if (rc) return fail(nullptr, rc, msg);
-    if (max_nvec < 1) return fail(nullptr, CHFSI_E_ARG, "max_nvec must be >= 1");
+    int64_t max_nvec, fblock;
+    chfsi_prec fprec;
+    if ((rc = plan_opts_check(po, max_nvec, fblock, fprec))) return rc;
     if (!V || !B) return fail(nullptr, CHFSI_E_ARG, "V and B must be device pointers");
-    Layout L = build_layout(m, max_nvec);
+    Layout L = build_layout(m, max_nvec, fblock, fprec);
     if (!persistent || persistent_bytes < L.persistent_bytes)
         return fail(nullptr, CHFSI_E_WORKSPACE, "persistent buffer too small: need " + std::to_string(L.persistent_bytes));
     if (!scratch || scratch_bytes < L.scratch_bytes)
@@ -723,6 +786,8 @@ int chfsi_setup(const chfsi_mesh *mesh, const double *V, const double *B, const 
     c->m = m;
     c->L = L;
     c->max_nvec = max_nvec;
+    c->filter_block = fblock;
+    c->filter_prec = fprec;
     c->pers = static_cast<char *>(persistent);
     c->scr = static_cast<char *>(scratch);
     c->blas = nullptr;
@@ -994,6 +1059,13 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
     if (o->degree < 1 || o->degree > kMaxDegree || o->max_iter < 1) return fail(c, CHFSI_E_ARG, "bad degree or max_iter");
     if (o->prec < CHFSI_FP64 || o->prec > CHFSI_BF16) return fail(c, CHFSI_E_ARG, "unknown precision");
     if (o->rr_mode < 0 || o->rr_mode > 2) return fail(c, CHFSI_E_ARG, "rr_mode must be 0, 1 or 2");
+    if (o->block < 0) return fail(c, CHFSI_E_ARG, "block must be >= 0");
+    const int64_t nb = o->block > 0 ? std::min<int64_t>(o->block, nsub) : std::min<int64_t>(nsub, c->filter_block);
+    if (nb > c->filter_block)
+        return fail(c, CHFSI_E_ARG, "block exceeds the filter_block the scratch was planned for");
+    if (2 * zblock_bytes(c->m, nb, o->prec != CHFSI_FP64) > c->L.zarea)
+        return fail(c, CHFSI_E_WORKSPACE, "the scratch cannot hold two recurrence blocks of " + std::to_string(nb) +
+                                              " columns in this precision (plan a wider filter precision)");
     if (!eigvals) return fail(c, CHFSI_E_ARG, "eigvals is NULL");
     size_t need = 0;
     if ((rc = chfsi_solve_workspace(c, nsub, ld, &need))) return rc;
@@ -1064,7 +1136,12 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
             break;
         }
         HIPCHK(c, hipEventRecord(ev[1], s));
-        if ((rc = filter_impl(c, o->prec, o->degree, bounds, X, ritz, R, X, nsub, ld, s))) { status = rc; break; }
+        // the filter is column-wise (Lambda_k is diagonal): blocks of nb columns
+        rc = CHFSI_OK;
+        for (int64_t b0 = 0; b0 < nsub && !rc; b0 += nb)
+            rc = filter_impl(c, o->prec, o->degree, bounds, X + b0, ritz + b0, R + b0, X + b0,
+                             std::min(nb, nsub - b0), ld, s);
+        if (rc) { status = rc; break; }
         HIPCHK(c, hipEventRecord(ev[2], s));
         if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { status = rc; break; }
         HIPCHK(c, launch_cell_op(c, CHFSI_FP64, MODE_MASS, 0, 1.0, X, MX, nsub, ld, s));

@@ -51,7 +51,9 @@ struct Layout {
     size_t persistent_bytes;
     // scratch
     size_t partial, dcoef;                   // complex128 [npairs|natoms][nbeta][max_nvec]
-    size_t Z;                                // 3 blocks complex128 [2M][max_nvec]
+    size_t Z;                                // two recurrence blocks [2M][filter_block] of the filter's
+                                             // complex type; also the rotation and Gram temporaries
+    size_t zarea;                            // bytes from Z to the end of the scratch buffer
     size_t lamk;                             // double [kMaxDegree+1][max_nvec]
     size_t small;                            // dense N x N matrices for RR
     size_t red;                              // reduction partials
@@ -75,6 +77,8 @@ struct chfsi_ctx {
     chfsi::Mesh m;
     chfsi::Layout L;
     int64_t max_nvec;
+    int64_t filter_block;     // columns of one filter pass (<= max_nvec)
+    chfsi_prec filter_prec;   // widest filter precision the scratch was sized for
     char *pers;
     char *scr;
     int64_t colour_ptr[9];

@@ -158,20 +158,31 @@ def min_image(d: np.ndarray, box: np.ndarray) -> np.ndarray:
 # fields
 # ----------------------------------------------------------------------------
 
-def gaussian_wells(pts: np.ndarray, centres: np.ndarray, depths: np.ndarray,
-                   box: np.ndarray, width: float = WELL_WIDTH) -> np.ndarray:
-    """V(r) = -sum_w d_w exp(-|r-c_w|^2/(2 width^2)) over the periodic images
-    within 10 widths (of the 27 nearest, an image shifted along a direction
-    whose half box exceeds 10 widths never comes that close and is skipped)."""
-    V = np.zeros(pts.shape[:-1])
+def well_potential(ncell, h, nq1: int, centres: np.ndarray, depths: np.ndarray, box: np.ndarray,
+                   width: float = WELL_WIDTH) -> np.ndarray:
+    """V[cell, site] = -sum_w d_w exp(-|r - c_w - L s|^2/(2 width^2)) over the
+    periodic images L s of each well that lie within 10 widths of the site.
+    Only the cells that can hold such a site are visited for each well (of
+    the 27 nearest images, an image shifted along a direction whose half box
+    exceeds 10 widths never comes that close and is skipped)."""
+    ncell = tuple(int(c) for c in ncell)
+    ncells = int(np.prod(ncell))
+    V = np.zeros((ncells, nq1 ** 3))
     reach = 10.0 * width
     shifts = [np.array([i, j, k], float) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)]
     shifts = [s for s in shifts if all(s[d] == 0 or 0.5 * box[d] <= reach for d in range(3))]
     for c, d in zip(centres, depths):
-        base = min_image(pts - c, box)
+        idx = []
+        for k in range(3):
+            lo = int(math.floor((c[k] - reach) / h[k]))
+            hi = int(math.floor((c[k] + reach) / h[k]))
+            idx.append(np.unique(np.mod(np.arange(lo, hi + 1), ncell[k])))
+        cand = (idx[0][:, None, None] + ncell[0] * (idx[1][None, :, None] + ncell[1] * idx[2][None, None, :])).ravel()
+        base = min_image(cell_quad_points(ncell, h, nq1, cand) - c, box)
         for s in shifts:
             r2 = np.sum((base + s * box) ** 2, axis=-1)
-            V -= d * np.exp(-r2 / (2.0 * width * width))
+            e = np.where(r2 <= reach * reach, np.exp(-r2 / (2.0 * width * width)), 0.0)
+            V[cand] -= d * e
     return V
 
 
@@ -315,17 +326,16 @@ def make_problem(ncell=(4, 4, 4), box=(8.0, 8.0, 8.0), degree=4, nq1=None,
     centres = r_wells.uniform(0.0, 1.0, size=(max(nwells, natoms), 3)) * box
     depths = r_wells.uniform(1.0, 3.0, size=max(nwells, natoms))
 
-    V = np.empty((ncells, nq))
+    if v_const is not None:
+        V = np.full((ncells, nq), float(v_const))
+    else:
+        V = well_potential(ncell, h, nq1, centres[:nwells], depths[:nwells], box)
     B = np.zeros((ncells, nq, 3))
     chunk = max(1, 200000 // nq)
     dirs_seed = int(r_bdir.integers(0, 2**31))
     for c0 in range(0, ncells, chunk):
         cells = np.arange(c0, min(ncells, c0 + chunk))
         pts = cell_quad_points(ncell, h, nq1, cells)
-        if v_const is not None:
-            V[cells] = float(v_const)
-        else:
-            V[cells] = gaussian_wells(pts, centres[:nwells], depths[:nwells], box)
         if bfield == "random":
             dirs = smooth_direction(pts, box, np.random.default_rng(dirs_seed))
             mag = np.random.default_rng([seed, 3, c0]).uniform(0.0, bmag, size=pts.shape[:-1])
@@ -398,6 +408,22 @@ def random_block(nrows: int, ncols: int, seed: int, ld: Optional[int] = None) ->
     g = np.random.default_rng([seed, 7])
     out = np.zeros((nrows, ld), complex)
     out[:, :ncols] = (g.standard_normal((nrows, ncols)) + 1j * g.standard_normal((nrows, ncols))) / math.sqrt(2.0)
+    return out
+
+
+def device_block(nrows: int, ncols: int, seed: int, dtype=None, device="cuda", chunk_rows: int = 1 << 20):
+    """Complex normal block [nrows, ncols] drawn on the device with torch's
+    seeded generator (real and imaginary parts of variance 1/2, like
+    random_block), in row chunks so that no temporary exceeds one chunk.
+    For blocks too large to draw on the host (the slab's 256 columns are
+    69 GB in complex128)."""
+    import torch
+    dtype = torch.complex128 if dtype is None else dtype
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    out = torch.empty((nrows, ncols), dtype=dtype, device=device)
+    for r0 in range(0, nrows, chunk_rows):
+        r1 = min(nrows, r0 + chunk_rows)
+        out[r0:r1] = torch.randn((r1 - r0, ncols), generator=g, dtype=torch.complex128, device=device).to(dtype)
     return out
 
 

@@ -46,8 +46,8 @@ def test_plan_sizes_and_validation(lib):
     pb, sb = C.c_size_t(), C.c_size_t()
     m = _mesh(binding)
     assert L.chfsi_plan(C.byref(m), None, 32, C.byref(pb), C.byref(sb)) == 0
-    # three recurrence blocks of 2M x 32 complex128 at least
-    assert sb.value >= 3 * 2 * 4096 * 32 * 16
+    # two recurrence blocks of 2M x 32 complex128 at least
+    assert sb.value >= 2 * 2 * 4096 * 32 * 16
     pb2, sb2 = C.c_size_t(), C.c_size_t()
     assert L.chfsi_plan(C.byref(m), None, 64, C.byref(pb2), C.byref(sb2)) == 0
     assert sb2.value > sb.value and pb2.value == pb.value
@@ -64,6 +64,35 @@ def test_plan_sizes_and_validation(lib):
         assert len(L.chfsi_last_error(None)) > 0
     assert L.chfsi_plan(C.byref(m), None, 0, C.byref(pb), C.byref(sb)) == binding.E_ARG
     assert L.chfsi_plan(None, None, 32, C.byref(pb), C.byref(sb)) == binding.E_ARG
+
+
+def test_plan_ex_filter_blocks(lib):
+    """chfsi_plan_ex: the recurrence area follows filter_block and the
+    filter's complex type; chfsi_plan is the FP64 plan of max_nvec columns."""
+    from paper_2605_30128_amd import binding
+    L = binding.load()
+    m = _mesh(binding)
+    rows = 2 * 4096
+
+    def plan(opts):
+        pb, sb = C.c_size_t(), C.c_size_t()
+        rc = L.chfsi_plan_ex(C.byref(m), None, C.byref(opts), C.byref(pb), C.byref(sb))
+        return rc, pb.value, sb.value
+
+    rc, pb0, sb0 = plan(binding.PlanOpts(64, 0, binding.FP64))
+    assert rc == 0
+    pbp, sbp = C.c_size_t(), C.c_size_t()
+    assert L.chfsi_plan(C.byref(m), None, 64, C.byref(pbp), C.byref(sbp)) == 0
+    assert (pbp.value, sbp.value) == (pb0, sb0)
+    rc, pb1, sb1 = plan(binding.PlanOpts(64, 0, binding.BF16))
+    assert rc == 0 and pb1 == pb0
+    # complex64 recurrence blocks: 2 x rows x 64 x 8 bytes less
+    assert sb0 - sb1 == 2 * rows * 64 * 8
+    rc, _, sb2 = plan(binding.PlanOpts(64, 16, binding.FP64))
+    assert rc == 0 and sb0 - sb2 == 2 * rows * (64 - 16) * 16
+    assert plan(binding.PlanOpts(64, 65, binding.FP64))[0] == binding.E_ARG
+    assert plan(binding.PlanOpts(0, 0, binding.FP64))[0] == binding.E_ARG
+    assert plan(binding.PlanOpts(64, 0, 7))[0] == binding.E_ARG
 
 
 def test_plan_rejects_bad_projectors(lib):
