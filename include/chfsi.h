@@ -228,6 +228,17 @@ int chfsi_rayleigh_ritz_general(chfsi_ctx *ctx, void *Y, void *HY, void *MY, int
 int chfsi_residual(chfsi_ctx *ctx, const void *HX, const void *MX, const double *ritz,
                    void *R, double *resnorm, int64_t nvec, int64_t ld, void *stream);
 
+/* chfsi_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same R and resnorm, computed by the same kernels in the same order, with
+ * the column-norm partials in a static device array of the library (8 MiB
+ * per GPU, held until the process ends) instead of the context's scratch.
+ * No allocation of any kind.  nvec <= 4096, else CHFSI_E_WORKSPACE.  The
+ * array is shared by every call on one GPU: calls that overlap on one GPU
+ * (different streams, threads or contexts) race on it. */
+int chfsi_residual_noalloc(chfsi_ctx *ctx, const void *HX, const void *MX, const double *ritz,
+                           void *R, double *resnorm, int64_t nvec, int64_t ld, void *stream);
+
 typedef struct {
     chfsi_prec prec;    /* precision of the filter's products */
     int degree;         /* Chebyshev degree q per iteration */

@@ -70,7 +70,7 @@ class PcgReport(C.Structure):
 SYMBOLS = [
     "chfsi_plan", "chfsi_setup", "chfsi_plan_ex", "chfsi_setup_ex", "chfsi_set_fields", "chfsi_apply_H", "chfsi_apply_M",
     "chfsi_apply_H_adjoint", "chfsi_estimate_bounds", "chfsi_filter", "chfsi_orthonormalize",
-    "chfsi_rayleigh_ritz", "chfsi_rayleigh_ritz_general", "chfsi_residual", "chfsi_solve_workspace", "chfsi_solve", "chfsi_info",
+    "chfsi_rayleigh_ritz", "chfsi_rayleigh_ritz_general", "chfsi_residual", "chfsi_residual_noalloc", "chfsi_solve_workspace", "chfsi_solve", "chfsi_info",
     "chfsi_mass_diag", "chfsi_profile_apply_H", "chfsi_bfp_bytes", "chfsi_bfp_encode", "chfsi_bfp_decode",
     "chfsi_apply_K", "chfsi_poisson_precond", "chfsi_poisson_solve",
     "chfsi_last_error", "chfsi_destroy",
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.chfsi_rayleigh_ritz.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
     L.chfsi_rayleigh_ritz_general.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp, vp]
     L.chfsi_residual.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp]
+    L.chfsi_residual_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp]
     L.chfsi_solve_workspace.argtypes = [vp, i64, i64, vp]
     L.chfsi_solve.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp, vp, vp, vp, C.c_size_t, vp]
     L.chfsi_info.argtypes = [vp, vp, vp, vp, vp]
@@ -312,12 +313,16 @@ class Chfsi:
                        _stream()))
         return ritz, R, res
 
-    def residual(self, HX, MX, ritz):
+    def residual(self, HX, MX, ritz, nvec=None, R=None, res=None, noalloc=False):
+        """R = HX - MX diag(ritz) and its column norms (chfsi_residual, or
+        chfsi_residual_noalloc with noalloc=True: static scratch)."""
         ld = self._block(HX, torch.complex128, "HX")
-        R = torch.empty_like(HX)
-        res = torch.empty(ld, dtype=torch.float64, device=HX.device)
-        self._check(self.L.chfsi_residual(self.ctx, _ptr(HX), _ptr(MX), _ptr(ritz.contiguous()), _ptr(R),
-                                          _ptr(res), ld, ld, _stream()))
+        nvec = ld if nvec is None else nvec
+        R = torch.empty_like(HX) if R is None else R
+        res = torch.empty(nvec, dtype=torch.float64, device=HX.device) if res is None else res
+        fn = self.L.chfsi_residual_noalloc if noalloc else self.L.chfsi_residual
+        self._check(fn(self.ctx, _ptr(HX), _ptr(MX), _ptr(ritz.contiguous()), _ptr(R), _ptr(res), nvec, ld,
+                       _stream()))
         return R, res
 
     # ------------------------------------------------------------ Poisson

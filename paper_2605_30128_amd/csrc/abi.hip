@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,7 +18,47 @@
 
 using namespace chfsi;
 
+// ---------------------------------------------------------------------------
+// Static scratch of chfsi_residual_noalloc: the column-norm partials
+// [kRowBlocks][nvec] of the residual, for callers that cannot allocate.
+// Each device holds its own copy of the array until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: the
+// device address of each GPU's copy is taken once with hipGetSymbolAddress
+// (with that device current) and only that address is passed to kernels.
+constexpr int64_t kNoAllocMaxCols = 4096;
+constexpr int64_t kNoAllocDoubles = (int64_t)chfsi::kRowBlocks * kNoAllocMaxCols;  // 8 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of the current device's static scratch, taken on first use
+// (hipGetSymbolAddress, never the array's name); nullptr and *err on failure.
+double *noalloc_scratch(hipError_t *err) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess && (dev < 0 || dev >= kMaxDevices)) e = hipErrorInvalidDevice;
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_noalloc_ptr[dev] = static_cast<double *>(p);
+    }
+    *err = hipSuccess;
+    return g_noalloc_ptr[dev];
+}
+
 
 thread_local std::string g_err;
 
@@ -871,6 +912,14 @@ int chfsi_setup_ex(const chfsi_mesh *mesh, const double *V, const double *B, con
         delete c;
         return fail(nullptr, CHFSI_E_DEVICE, em);
     }
+    {
+        // the static scratch of chfsi_residual_noalloc on this device
+        hipError_t ge = hipSuccess;
+        if (!noalloc_scratch(&ge)) {
+            delete c;
+            return fail(nullptr, CHFSI_E_DEVICE, std::string("static scratch address: ") + hipGetErrorString(ge));
+        }
+    }
     if (rocblas_create_handle(&c->blas) != rocblas_status_success) {
         delete c;
         return fail(nullptr, CHFSI_E_DEVICE, "rocblas_create_handle failed");
@@ -1036,6 +1085,26 @@ int chfsi_residual(chfsi_ctx *c, const void *HX, const void *MX, const double *r
     if (!ritz) return fail(c, CHFSI_E_ARG, "ritz is NULL");
     HIPCHK(c, launch_residual(2 * c->m.M, nvec, ld, (const cd *)HX, (const cd *)MX, ritz, (cd *)R,
                               c->S<double>(c->L.red), resnorm, S(stream)));
+    return CHFSI_OK;
+}
+
+int chfsi_residual_noalloc(chfsi_ctx *c, const void *HX, const void *MX, const double *ritz, void *R,
+                           double *resnorm, int64_t nvec, int64_t ld, void *stream) {
+    if (!c) return fail(nullptr, CHFSI_E_ARG, "ctx is NULL");
+    int rc;
+    if ((rc = check_block(c, HX, nvec, ld, "HX")) || (rc = check_block(c, MX, nvec, ld, "MX"))) return rc;
+    if (!ritz) return fail(c, CHFSI_E_ARG, "ritz is NULL");
+    if (nvec > kNoAllocMaxCols)
+        return fail(c, CHFSI_E_WORKSPACE, "chfsi_residual_noalloc: nvec " + std::to_string(nvec) +
+                                              " exceeds the static scratch (at most " +
+                                              std::to_string(kNoAllocMaxCols) + " columns)");
+    hipError_t ge = hipSuccess;
+    double *red = noalloc_scratch(&ge);
+    if (!red) return fail(c, CHFSI_E_DEVICE, std::string("static scratch address: ") + hipGetErrorString(ge));
+    // every partial [kRowBlocks][nvec] is written by the residual kernel
+    // before the norms read it, so nothing needs clearing
+    HIPCHK(c, launch_residual(2 * c->m.M, nvec, ld, (const cd *)HX, (const cd *)MX, ritz, (cd *)R, red, resnorm,
+                              S(stream)));
     return CHFSI_OK;
 }
 

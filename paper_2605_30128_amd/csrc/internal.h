@@ -17,6 +17,7 @@ constexpr int kCellThreads = 256;   // threads per workgroup of the FP64/FP32 ce
 constexpr int kMaxN = 512;          // nodes per cell (p <= 7)
 constexpr int kMaxBeta = 16;
 constexpr int kMaxDegree = 256;     // Chebyshev degree limit (Lambda_k table)
+constexpr int kRowBlocks = 256;     // row blocks of the column reductions (partials [kRowBlocks][nvec])
 constexpr int kPoiTab = 8 * 8 + 8 * 8 + 8;  // doubles of the Poisson 1D tables (nq1, n1 <= 8)
 
 // complex helpers ------------------------------------------------------------

@@ -8,7 +8,6 @@
 
 namespace chfsi {
 
-constexpr int kRowBlocks = 256;  // row blocks of the column reductions
 
 template <typename TZ> struct ZT;
 template <> struct ZT<cd> { using real = double; };
