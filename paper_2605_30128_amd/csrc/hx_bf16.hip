@@ -52,25 +52,32 @@ template <int NP> struct Bf16Cfg {
     static constexpr int KS = NP + 8;                 // padded row of the block (bf16)
     static constexpr int CHUNKS = NP * (kSlice / 8);  // 16-byte pieces of one slice
     static constexpr int SITER = (CHUNKS + kBfThreads - 1) / kBfThreads;
+    static constexpr int SCOLS = SITER * kBfThreads / 4;  // columns of an LDS slice buffer (>= NP)
 };
 
-// stage one k-slice [NP columns][32 k] of a [column][k] table into LDS
+// stage one k-slice [NP columns][32 k] of a [column][k] table into LDS.
+// The loads are unconditional (a thread past the slice reloads its last
+// chunk): without branches around them the compiler can wait for exactly
+// the loads a slice needs, so the prefetch two slices ahead stays in flight.
 template <int NP>
 __device__ __forceinline__ void slice_load(u4 (&r)[Bf16Cfg<NP>::SITER], const __bf16 *B, int k0, int ldb = NP) {
     using C = Bf16Cfg<NP>;
 #pragma unroll
     for (int u = 0; u < C::SITER; ++u) {
-        const int c = threadIdx.x + u * kBfThreads;
-        if (c < C::CHUNKS) r[u] = *reinterpret_cast<const u4 *>(B + (size_t)(c >> 2) * ldb + k0 + 8 * (c & 3));
+        const int c = min((int)threadIdx.x + u * kBfThreads, C::CHUNKS - 1);
+        r[u] = *reinterpret_cast<const u4 *>(B + (size_t)(c >> 2) * ldb + k0 + 8 * (c & 3));
     }
 }
+// The LDS slice buffers have SCOLS >= NP columns, so every thread stores all
+// its chunks without a branch (chunks past the slice land in the unread
+// padding columns).
 template <int NP>
 __device__ __forceinline__ void slice_store(const u4 (&r)[Bf16Cfg<NP>::SITER], __bf16 *bs) {
     using C = Bf16Cfg<NP>;
 #pragma unroll
     for (int u = 0; u < C::SITER; ++u) {
         const int c = threadIdx.x + u * kBfThreads;
-        if (c < C::CHUNKS) *reinterpret_cast<u4 *>(bs + slice_pos(c >> 2, c & 3)) = r[u];
+        *reinterpret_cast<u4 *>(bs + slice_pos(c >> 2, c & 3)) = r[u];
     }
 }
 
@@ -105,8 +112,8 @@ __device__ __forceinline__ void slice_step(f4 (*acc)[Bf16Cfg<NP>::NTW], const __
                                            const u4 (&nxt)[Bf16Cfg<NP>::SITER], int mh, int nt0, int lane) {
     constexpr int S = NP / kSlice;
     if (s + 2 < S) slice_load<NP>(frees, B, (s + 2) * kSlice);
-    slice_mfma<NP>(acc, as, bs + (s & 1) * NP * kSliceRow, s, mh, nt0, lane);
-    if (s + 1 < S) slice_store<NP>(nxt, bs + ((s + 1) & 1) * NP * kSliceRow);
+    slice_mfma<NP>(acc, as, bs + (s & 1) * Bf16Cfg<NP>::SCOLS * kSliceRow, s, mh, nt0, lane);
+    if (s + 1 < S) slice_store<NP>(nxt, bs + ((s + 1) & 1) * Bf16Cfg<NP>::SCOLS * kSliceRow);
     __syncthreads();
 }
 
@@ -123,7 +130,8 @@ __device__ __forceinline__ void panel_bf16(f4 (*acc)[Bf16Cfg<NP>::NTW], const __
     if (S > 1) slice_load<NP>(r1, B, kSlice);
     slice_store<NP>(r0, bs);
     __syncthreads();
-#pragma unroll 1
+    // fully unrolled: every load and wait of the pipeline is static
+#pragma unroll
     for (int s = 0; s < S; s += 2) {
         slice_step<NP>(acc, as, B, bs, s, r0, r1, mh, nt0, lane);
         if (s + 1 < S) slice_step<NP>(acc, as, B, bs, s + 1, r1, r0, mh, nt0, lane);
@@ -137,7 +145,7 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a) {
     static_assert(NP % 32 == 0, "k steps of 32");
     // the gathered block and the table slices; after the last panel the
     // whole area stages the result for the assembly
-    constexpr int XSB = CB * KS * 2, BSB = 2 * NP * kSliceRow * 2;
+    constexpr int XSB = CB * KS * 2, BSB = 2 * C::SCOLS * kSliceRow * 2;
     __shared__ __attribute__((aligned(16))) char smem[XSB + BSB];
     __bf16 *xs = reinterpret_cast<__bf16 *>(smem), *bs = reinterpret_cast<__bf16 *>(smem + XSB);
     __shared__ int ijk[NP];
@@ -153,27 +161,32 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int mh = wave % C::RG, nt0 = (wave / C::RG) * NTW;
 
-    {
-        const float *dinv = (a.flags & FLAG_DINV) ? reinterpret_cast<const float *>(a.dinv) : nullptr;
-        for (int I = tid; I < NP; I += kBfThreads) {
-            const int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
-            const int c = i | (j << 8) | (k << 16);
-            ijk[I] = c;
-            int64_t g = 0;
-            if (I < a.n) g = gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
-            grow[I] = (int)(2 * g);
-            gsc[I] = (dinv && I < a.n) ? dinv[g] : 1.0f;
-            reinterpret_cast<f4 *>(ws)[I] = reinterpret_cast<const f4 *>(a.W)[(size_t)e * NP + I];
-        }
+    // node tables of the cell (arithmetic only); its D^-1 and w|J| (V, B)
+    // values are fetched now but stored to LDS only after the gather's loads
+    // are issued, so their latency overlaps the gather
+    static_assert(NP <= kBfThreads, "one thread per node of the cell");
+    float dv = 1.0f;
+    f4 wv = f4{0.f, 0.f, 0.f, 0.f};
+    if (tid < NP) {
+        const int I = tid;
+        const int i = I % a.n1, j = (I / a.n1) % a.n1, k = I / (a.n1 * a.n1);
+        const int c = i | (j << 8) | (k << 16);
+        ijk[I] = c;
+        int64_t g = 0;
+        if (I < a.n) g = gnode_of(c, ex, ey, ez, a.p, a.Nx, a.Ny, a.Nz);
+        grow[I] = (int)(2 * g);
+        if ((a.flags & FLAG_DINV) && I < a.n) dv = reinterpret_cast<const float *>(a.dinv)[g];
+        wv = reinterpret_cast<const f4 *>(a.W)[(size_t)e * NP + I];
     }
     __syncthreads();
     {
         // gather: a task is (vector v, spin s, eight consecutive nodes): eight
         // 8-byte row loads (the 16 vectors of a lane group read a 128-byte
-        // row piece), all issued before the first LDS store; the eight real
-        // parts and the eight imaginary parts then go to LDS as one 16-byte
-        // store each.  With rows KS apart the 16 stores of a pass fall on
-        // disjoint banks at NP = 352.
+        // row piece), the loads of a half of the vectors issued at once and
+        // without branches (a load past the block or the cell reads element 0
+        // and is discarded); the eight real parts and the eight imaginary
+        // parts then go to LDS as one 16-byte store each.  With rows KS apart the 16
+        // stores of a pass fall on disjoint banks at NP = 352.
         const cf *X = reinterpret_cast<const cf *>(a.X);
         constexpr int NH = VB >= 32 ? 2 : 1, HV = VB / NH, NB8 = NP / 8;
         constexpr int TASKS = HV * 2 * NB8, ITER = (TASKS + kBfThreads - 1) / kBfThreads;
@@ -184,16 +197,22 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a) {
 #pragma unroll
             for (int u = 0; u < ITER; ++u) {
                 const int idx = tid + u * kBfThreads;
-                const int v = h * HV + idx % HV, sp = (idx / HV) & 1, b = idx / (2 * HV);
+                const int v = h * HV + idx % HV, sp = (idx / HV) & 1, b = min(idx / (2 * HV), NB8 - 1);
                 const int64_t col = vb * VB + v;
                 const bool ok = idx < TASKS && col < a.nvec;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int I = 8 * b + k;
-                    z[u][k] = cf{0.f, 0.f};
-                    if (ok && I < a.n) z[u][k] = X[(int64_t)(grow[I] + sp) * a.ld + col];
+                    const bool valid = ok && I < a.n;
+                    const cf t = X[valid ? (int64_t)(grow[I] + sp) * a.ld + col : 0];
+                    z[u][k] = valid ? t : cf{0.f, 0.f};
                 }
             }
+            if (h == 0 && tid < NP) {
+                gsc[tid] = dv;
+                reinterpret_cast<f4 *>(ws)[tid] = wv;
+            }
+            if (h == 0) __syncthreads();
 #pragma unroll
             for (int u = 0; u < ITER; ++u) {
                 const int idx = tid + u * kBfThreads;
@@ -345,7 +364,7 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a) {
             }
         }
         __syncthreads();
-        constexpr int PIECES = NP * VR, PIT = (PIECES + kBfThreads - 1) / kBfThreads, PG = 4;
+        constexpr int PIECES = NP * VR, PIT = (PIECES + kBfThreads - 1) / kBfThreads, PG = PIT;
 #pragma unroll
         for (int u0 = 0; u0 < PIT; u0 += PG) {
             f4 old[PG];
