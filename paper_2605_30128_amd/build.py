@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libchfsi.so")
-SOURCES = ["abi.hip", "hx_kernels.hip", "hx_bf16.hip", "vec_kernels.hip", "dense_kernels.hip", "bfp_kernels.hip",
+SOURCES = ["abi.hip", "hx_kernels.hip", "hx_bf16.hip", "hx_bf16_epi.hip", "vec_kernels.hip", "dense_kernels.hip", "bfp_kernels.hip",
            "poisson.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

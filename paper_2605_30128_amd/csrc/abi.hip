@@ -742,11 +742,11 @@ int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds,
         const double a = 2.0 * sn / e;
         // Z_{k+1} = -a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k
         if (Zp) Zn = Zp;  // Z_{k+1} over Z_{k-1}
-        HIPCHK(c, launch_filter_init_ld(rows, nvec, nvec, ld, z32, Zn, Zc, Zp, R, -a * cc, -sk * sn,
-                                        lamk + (int64_t)k * nvec, a, s));
-        // Z_{k+1} += a H D^{-1} Z_k
+        // Z_{k+1} = a H D^{-1} Z_k - a c Z_k - s_k s_{k+1} Z_{k-1} + a R Lambda_k in one pass of the cell
+        // operator: the first colour to reach a node writes all four terms, later colours add a H D^{-1} Z_k
         if (nl) HIPCHK(c, launch_nonlocal_coeffs(c, prec, FLAG_DINV, Zc, nvec, nvec, s));
-        HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_ACCUM | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s));
+        const EpiArgs ep{Zp, R, ld, lamk + (int64_t)k * nvec, -a * cc, -sk * sn};
+        HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_EPI | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s, &ep));
         Zp = Zc;
         Zc = Zn;
         sk = sn;

@@ -161,7 +161,7 @@ __device__ __forceinline__ void mfma_panel(typename MM<T>::acc *acc, const T *as
 // rows x NP columns of the block MT (16-row tiles) x WN (column groups of
 // NTW 16-column tiles).
 template <typename T, int MT, int NP>
-__global__ __launch_bounds__(kCellThreads) void cell_kernel(CellParams a) {
+__global__ __launch_bounds__(kCellThreads) void cell_kernel(CellParams a, EpiArgs ep) {
     using TC = typename Cplx<T>::type;
     using acc_t = typename MM<T>::acc;
     constexpr int CB = 16 * MT, VB = 4 * MT;
@@ -249,12 +249,18 @@ __global__ __launch_bounds__(kCellThreads) void cell_kernel(CellParams a) {
     }
 
     // colour-ordered assembly: the previous values of all the lane's nodes
-    // are loaded before any is written back
+    // are loaded before any is written back.  With FLAG_EPI the first touch
+    // of a node adds the filter step's recurrence terms instead, beta Z_k +
+    // gamma Z_{k-1} + alpha lam R, formed in double from Z_k (the input
+    // block), Z_{k-1} (which the output may overwrite: it is read first) and R.
     TC *Y = reinterpret_cast<TC *>(a.Y);
     const int64_t col = vb * VB + 4 * m + (lane >> 4);
     if (col < a.nvec) {
         const T al = (T)a.alpha;
-        const bool accum = (a.flags & FLAG_ACCUM) != 0;
+        const bool accum = (a.flags & FLAG_ACCUM) != 0, epi = (a.flags & FLAG_EPI) != 0;
+        const TC *Zk = reinterpret_cast<const TC *>(a.X), *Zkm = reinterpret_cast<const TC *>(ep.Zkm);
+        const cd *R = ep.R;
+        const double dl = epi ? a.alpha * ep.lam[col] : 0.0;
         int64_t off[NTW];
         TC o0[NTW], o1[NTW];
 #pragma unroll
@@ -270,6 +276,18 @@ __global__ __launch_bounds__(kCellThreads) void cell_kernel(CellParams a) {
                 if (!first_touch(c, a.p, a.px, a.py, a.pz, accum)) {
                     o0[t] = Y[off[t]];
                     o1[t] = Y[off[t] + a.ld];
+                } else if (epi) {
+                    const TC k0 = Zk[off[t]], k1 = Zk[off[t] + a.ld];
+                    const cd r0 = R[row * ep.ldr + col], r1 = R[(row + 1) * ep.ldr + col];
+                    double e0x = dl * r0.x + ep.beta * (double)k0.x, e0y = dl * r0.y + ep.beta * (double)k0.y;
+                    double e1x = dl * r1.x + ep.beta * (double)k1.x, e1y = dl * r1.y + ep.beta * (double)k1.y;
+                    if (Zkm) {
+                        const TC m0 = Zkm[off[t]], m1 = Zkm[off[t] + a.ld];
+                        e0x += ep.gamma * (double)m0.x; e0y += ep.gamma * (double)m0.y;
+                        e1x += ep.gamma * (double)m1.x; e1y += ep.gamma * (double)m1.y;
+                    }
+                    o0[t] = TC{(T)e0x, (T)e0y};
+                    o1[t] = TC{(T)e1x, (T)e1y};
                 }
             }
         }
@@ -758,7 +776,7 @@ __global__ void dinv_kernel(const double *D, double *d64, float *d32, int64_t M)
 // ---------------------------------------------------------------------------
 template <typename T, int MT, int NP>
 static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha, const void *X,
-                           void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+                           void *Y, int64_t nvec, int64_t ld, hipStream_t s, const EpiArgs *epi) {
     const Mesh &m = c->m;
     const Layout &L = c->L;
     constexpr bool dbl = sizeof(T) == 8;
@@ -776,6 +794,8 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
     a.alpha = alpha;
     a.mode = mode;
     a.flags = flags;
+    if ((flags & FLAG_EPI) && !epi) return hipErrorInvalidValue;
+    const EpiArgs ep = (flags & FLAG_EPI) ? *epi : EpiArgs{};
     if ((flags & FLAG_NLOC) && m.npairs > 0 && mode == MODE_HAM) {
         a.cell_pair_ptr = c->P<int>(L.cell_pair_ptr);
         a.cell_pairs = c->P<int>(L.cell_pairs);
@@ -795,7 +815,7 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
         a.cells = c->P<int>(L.colour_cells) + c->colour_ptr[col];
         a.ncl = ncl;
         a.px = col & 1; a.py = (col >> 1) & 1; a.pz = (col >> 2) & 1;
-        hipLaunchKernelGGL((cell_kernel<T, MT, NP>), dim3((unsigned)(ncl * nvb)), dim3(kCellThreads), 0, s, a);
+        hipLaunchKernelGGL((cell_kernel<T, MT, NP>), dim3((unsigned)(ncl * nvb)), dim3(kCellThreads), 0, s, a, ep);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -874,16 +894,17 @@ static hipError_t run_adjoint(const chfsi_ctx *c, const void *X, const void *G, 
     }
 
 hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
-                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s, const EpiArgs *epi) {
     if (prec == CHFSI_FP64) {
-        CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s)));
+        CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s,
+                                                                      epi)));
     }
-    if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s);
+    if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s, epi);
     // float: 16 vectors per workgroup, except at p = 7 where the two
     // accumulator sets of 32 column tiles per wave would spill; there 8
     // vectors per workgroup and two column groups of 16 tiles
     CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, NP == 512 ? 2 : 4, NP>(c, mode, flags, alpha, X, Y, nvec,
-                                                                                  ld, s)));
+                                                                                  ld, s, epi)));
 }
 
 // the projection of the bfloat16 path runs in float (complex64 blocks)

@@ -103,13 +103,28 @@ enum : int {
     FLAG_ACCUM = 1,     // Y += alpha * (.) at every node (else first touch writes)
     FLAG_DINV = 2,      // gather D^{-1} X
     FLAG_NLOC = 4,      // add the spin-orbit epilogue (needs dcoef)
+    FLAG_EPI = 8,       // first touch writes alpha (.) + the recurrence terms of EpiArgs
+};
+
+// The recurrence terms of one filter step (eq. rChFSIrecurrence) that the
+// cell operator's first touch of a node adds to alpha H D^{-1} Z_k:
+// beta Z_k + gamma Z_{k-1} + alpha lam[c] R (formed in double).  Z_k is the
+// operator's input block; Zkm (Z_{k-1}, nullable) has its leading dimension
+// and may be the output block itself (read before it is overwritten).
+struct EpiArgs {
+    const void *Zkm;
+    const cd *R;
+    int64_t ldr;
+    const double *lam;
+    double beta, gamma;
 };
 
 // apply the cell operator for all 8 colours: Y (+)= alpha * Op(X)
 hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
-                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s);
+                          const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s,
+                          const EpiArgs *epi = nullptr);
 hipError_t launch_cell_op_bf16(const chfsi_ctx *c, int mode, int flags, double alpha, const void *X,
-                               void *Y, int64_t nvec, int64_t ld, hipStream_t s);
+                               void *Y, int64_t nvec, int64_t ld, hipStream_t s, const EpiArgs *epi = nullptr);
 // nonlocal projection + per-atom reduction with Delta: dcoef = Delta * P^H X
 hipError_t launch_nonlocal_coeffs(const chfsi_ctx *c, chfsi_prec prec, int flags, const void *X,
                                   int64_t nvec, int64_t ld, hipStream_t s);
