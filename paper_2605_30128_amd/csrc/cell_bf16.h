@@ -202,9 +202,10 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
         constexpr int NH = VB >= 32 ? 2 : 1, HV = VB / NH, NB8 = NP / 8;
         constexpr int TASKS = HV * 2 * NB8, ITER = (TASKS + kBfThreads - 1) / kBfThreads;
         static_assert(NP % 8 == 0 && (KS * 2) % 16 == 0, "16-byte node pieces");
+        // both halves' loads are in flight before the first conversion
+        cf z[NH][ITER][8];
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
-            cf z[ITER][8];
 #pragma unroll
             for (int u = 0; u < ITER; ++u) {
                 const int idx = tid + u * kBfThreads;
@@ -216,14 +217,17 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
                     const int I = 8 * b + k;
                     const bool valid = ok && I < a.n;
                     const cf t = X[valid ? (int64_t)(grow[I] + sp) * a.ld + col : 0];
-                    z[u][k] = valid ? t : cf{0.f, 0.f};
+                    z[h][u][k] = valid ? t : cf{0.f, 0.f};
                 }
             }
-            if (h == 0 && tid < NP) {
-                gsc[tid] = dv;
-                reinterpret_cast<f4 *>(ws)[tid] = wv;
-            }
-            if (h == 0) __syncthreads();
+        }
+        if (tid < NP) {
+            gsc[tid] = dv;
+            reinterpret_cast<f4 *>(ws)[tid] = wv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
 #pragma unroll
             for (int u = 0; u < ITER; ++u) {
                 const int idx = tid + u * kBfThreads;
@@ -233,8 +237,8 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const float sc = gsc[8 * b + k];
-                    re[k] = (__bf16)(z[u][k].x * sc);
-                    im[k] = (__bf16)(z[u][k].y * sc);
+                    re[k] = (__bf16)(z[h][u][k].x * sc);
+                    im[k] = (__bf16)(z[h][u][k].y * sc);
                 }
                 *reinterpret_cast<bf8 *>(xs + (4 * v + 2 * sp) * KS + 8 * b) = re;
                 *reinterpret_cast<bf8 *>(xs + (4 * v + 2 * sp + 1) * KS + 8 * b) = im;
@@ -254,6 +258,36 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
 #pragma unroll
             for (int t = 0; t < NTW; ++t) tq[mm][t] = f4{0, 0, 0, 0};
         panel_bf16<NP>(tq, xs, reinterpret_cast<const __bf16 *>(a.BphiT), bs, mh, nt0, lane);
+        // spin-orbit apply at the quadrature points, T += w|J| phi_a d_a: K=32
+        // MFMA steps over k = (j, spin s', re|im part) with
+        // A[(v, s, r)][k] = delta_{s s'} (re/im part of d_j(v)); the pair's
+        // [q][k] table slice is staged through LDS like the panels' tables.
+        // A unit is one 32-wide k slice of one pair; each unit's table slice
+        // and coefficients are loaded one unit ahead (the first before the
+        // 2x2 term), so their latency overlaps the previous unit's MFMAs.
+        const bool soc = (a.flags & FLAG_NLOC) && a.cell_pair_ptr;
+        const int pb = soc ? a.cell_pair_ptr[e] : 0, pe = soc ? a.cell_pair_ptr[e + 1] : 0;
+        const int nks = soc ? a.ldw / kSlice : 1, units = (pe - pb) * nks;
+        const int vr = (lane & 15) >> 2, comp = lane & 3, sA = comp >> 1, rA = comp & 1;
+        const int cn = lane & 15, kq = 8 * (lane >> 4);
+        u4 rs[C::SITER];
+        cf dd[MH][2];
+        auto load_unit = [&](int u) {
+            const int pair = a.cell_pairs[pb + u / nks], ks = (u % nks) * kSlice;
+            const int atom = a.pair_atom[pair];
+            slice_load<NP>(rs, reinterpret_cast<const __bf16 *>(a.P) + (size_t)pair * NP * a.ldw, ks, a.ldw);
+            const cf *dc = reinterpret_cast<const cf *>(a.dcoef) + (size_t)atom * a.nbeta * a.ldd;
+#pragma unroll
+            for (int mm = 0; mm < MH; ++mm) {
+                const int64_t colA = vb * VB + 4 * (mh * MH + mm) + vr;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int j = (ks + kq) / 4 + hh;
+                    dd[mm][hh] = (j < a.nbeta && colA < a.nvec) ? dc[(size_t)j * a.ldd + colA] : cf{0.f, 0.f};
+                }
+            }
+        };
+        if (units > 0) load_unit(0);
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             const int q = (nt0 + t) * 16 + (lane & 15);
@@ -268,55 +302,37 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
                 tq[mm][t][3] = bx * ui + by * ur + (v - bz) * di;
             }
         }
-        // spin-orbit apply at the quadrature points, T += w|J| phi_a d_a: K=32
-        // MFMA steps over k = (j, spin s', re|im part) with
-        // A[(v, s, r)][k] = delta_{s s'} (re/im part of d_j(v)); the pair's
-        // [q][k] table slice is staged through LDS like the panels' tables
-        if ((a.flags & FLAG_NLOC) && a.cell_pair_ptr) {
-            const int pb = a.cell_pair_ptr[e], pe = a.cell_pair_ptr[e + 1];
-            const int r = lane & 15, vr = r >> 2, comp = r & 3, sA = comp >> 1, rA = comp & 1;
-            const int cn = lane & 15, kq = 8 * (lane >> 4);
-            u4 rs[C::SITER];
-            for (int pp = pb; pp < pe; ++pp) {
-                const int pair = a.cell_pairs[pp];
-                const int atom = a.pair_atom[pair];
-                const __bf16 *wp = reinterpret_cast<const __bf16 *>(a.P) + (size_t)pair * NP * a.ldw;
-                const cf *dc = reinterpret_cast<const cf *>(a.dcoef) + (size_t)atom * a.nbeta * a.ldd;
-                for (int ks = 0; ks < a.ldw; ks += 32) {
-                    slice_load<NP>(rs, wp, ks, a.ldw);
-                    bf8 av[MH];
+        for (int u = 0; u < units; ++u) {
+            bf8 av[MH];
 #pragma unroll
-                    for (int mm = 0; mm < MH; ++mm) {
-                        const int64_t colA = vb * VB + 4 * (mh * MH + mm) + vr;
+            for (int mm = 0; mm < MH; ++mm) {
 #pragma unroll
-                        for (int hh = 0; hh < 2; ++hh) {
-                            const int j = (ks + kq) / 4 + hh;
-                            cf d = {0.f, 0.f};
-                            if (j < a.nbeta && colA < a.nvec) d = dc[(size_t)j * a.ldd + colA];
+                for (int hh = 0; hh < 2; ++hh) {
+                    const cf d = dd[mm][hh];
 #pragma unroll
-                            for (int sp = 0; sp < 2; ++sp) {
-                                float re = 0.f, im = 0.f;  // the (part = re, part = im) entries
-                                if (sp == sA) {
-                                    re = rA == 0 ? d.x : d.y;
-                                    im = rA == 0 ? -d.y : d.x;
-                                }
-                                av[mm][4 * hh + 2 * sp] = (__bf16)re;
-                                av[mm][4 * hh + 2 * sp + 1] = (__bf16)im;
-                            }
+                    for (int sp = 0; sp < 2; ++sp) {
+                        float re = 0.f, im = 0.f;  // the (part = re, part = im) entries
+                        if (sp == sA) {
+                            re = rA == 0 ? d.x : d.y;
+                            im = rA == 0 ? -d.y : d.x;
                         }
+                        av[mm][4 * hh + 2 * sp] = (__bf16)re;
+                        av[mm][4 * hh + 2 * sp + 1] = (__bf16)im;
                     }
-                    slice_store<NP>(rs, bs);
-                    __syncthreads();
-#pragma unroll
-                    for (int t = 0; t < NTW; ++t) {
-                        const bf8 bv = *reinterpret_cast<const bf8 *>(bs + slice_pos(16 * (nt0 + t) + cn, kq >> 3));
-#pragma unroll
-                        for (int mm = 0; mm < MH; ++mm)
-                            tq[mm][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mm], bv, tq[mm][t], 0, 0, 0);
-                    }
-                    __syncthreads();
                 }
             }
+            // the previous unit's MFMAs (or panel 1) ended with a barrier: the slice buffer is free
+            slice_store<NP>(rs, bs);
+            if (u + 1 < units) load_unit(u + 1);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) {
+                const bf8 bv = *reinterpret_cast<const bf8 *>(bs + slice_pos(16 * (nt0 + t) + cn, kq >> 3));
+#pragma unroll
+                for (int mm = 0; mm < MH; ++mm)
+                    tq[mm][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[mm], bv, tq[mm][t], 0, 0, 0);
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int mm = 0; mm < MH; ++mm)
