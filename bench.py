@@ -181,7 +181,7 @@ def cell_roofline(p, prec, nvec, ms_cell, launches, config):
     return roof
 
 
-def slab_leg(nvec=256, degree=40, reps=3):
+def slab_leg(nvec=256, degree=40, reps=3, precs=("fp64", "fp32", "bf16"), filters=True):
     """The largest one-GPU share (periodic slab, 32 x 32 x 24 cells, p = 7,
     8,429,568 nodes, 256 atoms x 8 projectors), one block of nvec vectors:
     H X in FP64, FP32 and bfloat16 with the cell kernel's roofline, and the
@@ -198,8 +198,8 @@ def slab_leg(nvec=256, degree=40, reps=3):
     op = binding.Chfsi(p, max_nvec=nvec, filter_block=nvec, filter_prec="bf16")
     out = {"nodes": p.nnodes, "dofs": p.ndof, "cells": p.ncells, "degree": p.degree, "vectors": nvec,
            "hx_gdofvec_per_s": {}, "hx_profile_ms": {}, "roofline": {}}
-    X = synth.device_block(p.ndof, nvec, 801)
-    for prec in ("fp64", "fp32", "bf16"):
+    X = synth.device_block(p.ndof, nvec, 801, dtype=torch.complex128 if "fp64" in precs else torch.complex64)
+    for prec in precs:
         if prec != "fp64" and X.dtype == torch.complex128:
             X = X.to(torch.complex64)
             torch.cuda.empty_cache()
@@ -215,6 +215,8 @@ def slab_leg(nvec=256, degree=40, reps=3):
         del Y
     del X
     torch.cuda.empty_cache()
+    if not filters:
+        return out
     v0 = synth.device_block(p.ndof, 1, 802)[:, 0].contiguous()
     lmax = op.estimate_bounds(v0, 20)
     del v0
@@ -492,6 +494,8 @@ def main():
     ap.add_argument("--no-gate", action="store_true", help="skip the mid-size mixed-vs-FP64 convergence leg")
     ap.add_argument("--no-slab", action="store_true", help="skip the largest-share (slab) leg")
     ap.add_argument("--slab-only", action="store_true", help="run only the slab leg")
+    ap.add_argument("--slab-precs", default="fp64,fp32,bf16", help="--slab-only: H X precisions")
+    ap.add_argument("--slab-no-filter", action="store_true", help="--slab-only: H X only (for counter runs)")
     ap.add_argument("--poisson-only", action="store_true", help="run only the Poisson leg")
     ap.add_argument("--no-pcg", action="store_true", help="Poisson leg: K x only")
     ap.add_argument("--kx-reps", type=int, default=50)
@@ -525,7 +529,15 @@ def main():
         print(json.dumps({"poisson": poi}), flush=True)
         return
     if args.slab_only:
-        print(json.dumps({"slab": slab_leg()}), flush=True)
+        if args.slab_no_filter:
+            # memory-counter calibration: a fill writes 2^30 bytes, a sum reads them
+            a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+            a.fill_(1.0)
+            a.sum().item()
+            torch.cuda.synchronize()
+            del a
+        print(json.dumps({"slab": slab_leg(precs=tuple(args.slab_precs.split(",")),
+                                           filters=not args.slab_no_filter)}), flush=True)
         return
     cfg = synth.CONFIGS[args.config]
     t0 = time.perf_counter()
