@@ -40,17 +40,24 @@ constexpr int kSliceRow = 32;    // LDS row of a staged slice (bf16): one column
 // disjoint LDS banks without padding
 __device__ __forceinline__ int slice_pos(int col, int q) { return col * kSliceRow + 8 * (q ^ ((col >> 2) & 3)); }
 
-constexpr int kBfWaves = 8;                  // waves per workgroup: 4 row groups x 2 column halves
+constexpr int kBfWaves = 8;                  // waves per workgroup: row groups x column groups
 constexpr int kBfThreads = 64 * kBfWaves;
 
 template <int NP> struct Bf16Cfg {
-    // 16-row tiles per wave: both accumulator sets (2 x MH x NP/32 tiles of
-    // 4 floats) must fit the 256 registers a lane has with two waves per SIMD
-    static constexpr int MH = NP <= 128 ? 4 : (NP <= 224 ? 3 : (NP <= 352 ? 2 : 1));
-    static constexpr int RG = kBfWaves / 2;           // row groups
+    // 16-row tiles per wave: the accumulators (MH x NTW tiles of 4 floats)
+    // and the bfloat16 copy of T must fit the 256 registers a lane has with
+    // two waves per SIMD
+    static constexpr int MH = NP <= 128 ? 4 : (NP <= 224 ? 3 : 2);
+    // row groups x column groups of waves: at NP = 512 (p = 7) a wave owns
+    // 2 row tiles x 8 column tiles; each table fragment it reads from LDS
+    // then feeds two MFMAs (4 row groups of one tile each and 16 column
+    // tiles took 1.3x longer per panel); 4 x 2 elsewhere
+    static constexpr int RG = NP == 512 ? 2 : 4;
+    static constexpr int CG = kBfWaves / RG;          // column groups
     static constexpr int CB = 16 * MH * RG;           // rows (real columns) per workgroup
     static constexpr int VB = CB / 4;                 // vectors per workgroup
-    static constexpr int NTW = NP / 32;               // 16-column tiles per wave
+    static constexpr int NTW = NP / (16 * CG);        // 16-column tiles per wave
+    static_assert(NTW * 16 * CG == NP, "column tiles split evenly");
     static constexpr int KS = NP + 8;                 // padded row of the block (bf16)
     static constexpr int CHUNKS = NP * (kSlice / 8);  // 16-byte pieces of one slice
     static constexpr int SITER = (CHUNKS + kBfThreads - 1) / kBfThreads;
@@ -108,23 +115,31 @@ __device__ __forceinline__ void slice_mfma(f4 (*acc)[Bf16Cfg<NP>::NTW], const __
 // slice s+1 in registers `nxt`; slice s+2 is fetched into `frees` (free
 // since its slice went to LDS one iteration earlier), so every slice has two
 // iterations to arrive from L2.
-template <int NP>
+template <int NP, class Hook>
 __device__ __forceinline__ void slice_step(f4 (*acc)[Bf16Cfg<NP>::NTW], const __bf16 *as, const __bf16 *B,
                                            __bf16 *bs, int s, u4 (&frees)[Bf16Cfg<NP>::SITER],
-                                           const u4 (&nxt)[Bf16Cfg<NP>::SITER], int mh, int nt0, int lane) {
+                                           const u4 (&nxt)[Bf16Cfg<NP>::SITER], int mh, int nt0, int lane,
+                                           Hook &hook) {
     constexpr int S = NP / kSlice;
     if (s + 2 < S) slice_load<NP>(frees, B, (s + 2) * kSlice);
+    if (s == (S > 2 ? S - 3 : 0)) hook();
     slice_mfma<NP>(acc, as, bs + (s & 1) * Bf16Cfg<NP>::SCOLS * kSliceRow, s, mh, nt0, lane);
     if (s + 1 < S) slice_store<NP>(nxt, bs + ((s + 1) & 1) * Bf16Cfg<NP>::SCOLS * kSliceRow);
     __syncthreads();
 }
 
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
 // acc[mm][t] += A(rows of tile mh*MH+mm) B(columns of tile nt0+t) over k in [0, NP),
 // A = as[row][k] in LDS, B = a [column][k] table staged slice by slice.
 // Ends with a barrier; starts assuming the caller's barrier made `as` valid.
-template <int NP>
+// `hook` runs once, right after the last slice's load is issued: loads it
+// issues complete in order after every slice, so the panel never waits for them.
+template <int NP, class Hook = NoHook>
 __device__ __forceinline__ void panel_bf16(f4 (*acc)[Bf16Cfg<NP>::NTW], const __bf16 *as, const __bf16 *B,
-                                           __bf16 *bs, int mh, int nt0, int lane) {
+                                           __bf16 *bs, int mh, int nt0, int lane, Hook &&hook = Hook{}) {
     using C = Bf16Cfg<NP>;
     constexpr int S = NP / kSlice;
     u4 r0[C::SITER], r1[C::SITER];
@@ -135,9 +150,21 @@ __device__ __forceinline__ void panel_bf16(f4 (*acc)[Bf16Cfg<NP>::NTW], const __
     // fully unrolled: every load and wait of the pipeline is static
 #pragma unroll
     for (int s = 0; s < S; s += 2) {
-        slice_step<NP>(acc, as, B, bs, s, r0, r1, mh, nt0, lane);
-        if (s + 1 < S) slice_step<NP>(acc, as, B, bs, s + 1, r1, r0, mh, nt0, lane);
+        slice_step<NP>(acc, as, B, bs, s, r0, r1, mh, nt0, lane, hook);
+        if (s + 1 < S) slice_step<NP>(acc, as, B, bs, s + 1, r1, r0, mh, nt0, lane, hook);
     }
+}
+
+// Rounds of the assembly: the fewest that split the VB vectors into rounds of
+// whole row tiles (four vectors each) whose [node][spin][vector] staging fits
+// `bytes` of LDS and whose vector count divides the thread count (so a
+// thread keeps its spin and columns across its pieces of a round).
+constexpr int assembly_rounds(int np, int vb, int bytes) {
+    for (int n = 1; n <= vb; ++n) {
+        const int vr = vb / n;
+        if (vb % n == 0 && vr % 4 == 0 && kBfThreads % vr == 0 && np * (4 * vr + 4) * 4 <= bytes) return n;
+    }
+    return 0;
 }
 
 // Two consecutive complex64 values of a row (one 16-byte load when the row
@@ -257,14 +284,14 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
         for (int mm = 0; mm < MH; ++mm)
 #pragma unroll
             for (int t = 0; t < NTW; ++t) tq[mm][t] = f4{0, 0, 0, 0};
-        panel_bf16<NP>(tq, xs, reinterpret_cast<const __bf16 *>(a.BphiT), bs, mh, nt0, lane);
         // spin-orbit apply at the quadrature points, T += w|J| phi_a d_a: K=32
         // MFMA steps over k = (j, spin s', re|im part) with
         // A[(v, s, r)][k] = delta_{s s'} (re/im part of d_j(v)); the pair's
         // [q][k] table slice is staged through LDS like the panels' tables.
         // A unit is one 32-wide k slice of one pair; each unit's table slice
-        // and coefficients are loaded one unit ahead (the first before the
-        // 2x2 term), so their latency overlaps the previous unit's MFMAs.
+        // and coefficients are loaded one unit ahead (the first during the
+        // Phi X panel, after its last table slice), so their latency overlaps
+        // the previous unit's MFMAs.
         const bool soc = (a.flags & FLAG_NLOC) && a.cell_pair_ptr;
         const int pb = soc ? a.cell_pair_ptr[e] : 0, pe = soc ? a.cell_pair_ptr[e + 1] : 0;
         const int nks = soc ? a.ldw / kSlice : 1, units = (pe - pb) * nks;
@@ -283,11 +310,15 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
 #pragma unroll
                 for (int hh = 0; hh < 2; ++hh) {
                     const int j = (ks + kq) / 4 + hh;
-                    dd[mm][hh] = (j < a.nbeta && colA < a.nvec) ? dc[(size_t)j * a.ldd + colA] : cf{0.f, 0.f};
+                    const bool ok = j < a.nbeta && colA < a.nvec;
+                    const cf d = dc[ok ? (size_t)j * a.ldd + colA : 0];
+                    dd[mm][hh] = ok ? d : cf{0.f, 0.f};
                 }
             }
         };
-        if (units > 0) load_unit(0);
+        panel_bf16<NP>(tq, xs, reinterpret_cast<const __bf16 *>(a.BphiT), bs, mh, nt0, lane, [&]() {
+            if (units > 0) load_unit(0);
+        });
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             const int q = (nt0 + t) * 16 + (lane & 15);
@@ -359,24 +390,45 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
         }
     }
     __syncthreads();
-    panel_bf16<NP>(y, xs, reinterpret_cast<const __bf16 *>(a.Bphi), bs, mh, nt0, lane);
-
     // colour-ordered assembly through LDS, in NR rounds of VR vectors: the
     // waves owning the round's row tiles write their results as
     // [node][spin][vector] complex values, then all threads update Y in
     // 16-byte pieces (two vectors of one spinor row), so every read-back and
-    // store covers whole rows of the vector block
-    constexpr int NR = NP * (4 * VB + 4) * 4 <= XSB + BSB ? 1 : 2;
+    // store covers whole rows of the vector block.  A thread's pieces of a
+    // round share its spin and its two columns (kBfThreads is a multiple of
+    // VR) and differ in the node.
+    constexpr int NR = assembly_rounds(NP, VB, XSB + BSB);
     constexpr int VR = VB / NR, TPR = VR / 4;        // vectors and row tiles per round
     constexpr int OS = 4 * VR + 4;                  // floats per node (padded to 16 bytes)
     static_assert(NP * OS * 4 <= XSB + BSB && VR % 2 == 0, "assembly staging fits the LDS area");
-    float *ob = reinterpret_cast<float *>(smem);
+    static_assert(kBfThreads % VR == 0, "a thread keeps its columns across pieces");
+    constexpr int PIECES = NP * VR, PIT = (PIECES + kBfThreads - 1) / kBfThreads;
+    panel_bf16<NP>(y, xs, reinterpret_cast<const __bf16 *>(a.Bphi), bs, mh, nt0, lane);
     cf *Y = reinterpret_cast<cf *>(a.Y);
-    const float al = (float)a.alpha;
     const bool accum = (a.flags & FLAG_ACCUM) != 0, even_ld = (a.ld & 1) == 0;
+    const int rem = tid % VR, sp = rem / (VR / 2), q = rem - sp * (VR / 2), J0 = tid / VR;
+    // read-backs of the pieces of round r (nodes an earlier colour wrote),
+    // issued before the round's staging.  (Issued during the last panel they
+    // would delay its table-slice waits, which count loads in issue order;
+    // issued a round ahead they spill.)
+    [[maybe_unused]] f4 rb[EPI ? 1 : PIT];
+    [[maybe_unused]] auto readback = [&](int r) {
+        const int64_t col = vb * VB + r * VR + 2 * q;
+        const bool colok = col < a.nvec, two = col + 1 < a.nvec;
+#pragma unroll
+        for (int u = 0; u < PIT; ++u) {
+            const int J = J0 + u * (kBfThreads / VR);
+            rb[u] = f4{0.f, 0.f, 0.f, 0.f};
+            if (J < a.n && colok && !first_touch(ijk[J], a.p, a.px, a.py, a.pz, accum))
+                rb[u] = load_pair(Y + (int64_t)(grow[J] + sp) * a.ld + col, even_ld, two);
+        }
+    };
+    float *ob = reinterpret_cast<float *>(smem);
+    const float al = (float)a.alpha;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         // panel 3 (or the previous round) ended with a barrier
+        if constexpr (!EPI) readback(r);
 #pragma unroll
         for (int mm = 0; mm < MH; ++mm) {
             const int rt = mh * MH + mm - r * TPR;
@@ -391,10 +443,19 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
             }
         }
         __syncthreads();
-        // with the recurrence terms (EPI) a first-touch piece reads Z_k, Z_{k-1}
-        // and R, so the loads go four pieces at a time; otherwise all of a
-        // round's read-backs are issued at once
-        constexpr int PIECES = NP * VR, PIT = (PIECES + kBfThreads - 1) / kBfThreads, PG = EPI ? 4 : PIT;
+        // with the recurrence terms (EPI) a first-touch piece reads Z_k,
+        // Z_{k-1} and R, so the loads go four pieces at a time; otherwise the
+        // round's read-backs are already in flight
+        constexpr int PG = EPI ? 4 : PIT;
+        const int64_t col = vb * VB + r * VR + 2 * q;
+        const bool colok = col < a.nvec, two = col + 1 < a.nvec, wide = even_ld && two;
+        [[maybe_unused]] double lam2[2] = {0.0, 0.0};
+        if constexpr (EPI) {
+            if (colok) {
+                lam2[0] = ep.lam[col];
+                if (two) lam2[1] = ep.lam[col + 1];
+            }
+        }
 #pragma unroll
         for (int u0 = 0; u0 < PIT; u0 += PG) {
             f4 old[PG];
@@ -403,67 +464,62 @@ __global__ __launch_bounds__(kBfThreads) void cell_kernel_bf16(CellParams a, Epi
             [[maybe_unused]] bool ft[EPI ? PG : 1];
 #pragma unroll
             for (int uu = 0; uu < PG; ++uu) {
-                const int c = tid + (u0 + uu) * kBfThreads;
-                const int J = c / VR, rem = c - J * VR, sp = rem / (VR / 2), q = rem - sp * (VR / 2);
-                const int64_t col = vb * VB + r * VR + 2 * q;
-                const bool valid = u0 + uu < PIT && c < PIECES && J < a.n && col < a.nvec;
-                old[uu] = f4{0.f, 0.f, 0.f, 0.f};
+                const int J = J0 + (u0 + uu) * (kBfThreads / VR);
+                const bool valid = u0 + uu < PIT && J < a.n && colok;
                 if constexpr (!EPI) {
-                    if (valid && !first_touch(ijk[J], a.p, a.px, a.py, a.pz, accum)) {
-                        const cf *src = Y + (int64_t)(grow[J] + sp) * a.ld + col;
-                        if (even_ld && col + 1 < a.nvec) {
-                            old[uu] = *reinterpret_cast<const f4 *>(src);
-                        } else {
-                            const cf z0 = src[0];
-                            const cf z1 = col + 1 < a.nvec ? src[1] : cf{0.f, 0.f};
-                            old[uu] = f4{z0.x, z0.y, z1.x, z1.y};
-                        }
-                    }
+                    old[uu] = rb[u0 + uu];
                 } else {
+                    old[uu] = f4{0.f, 0.f, 0.f, 0.f};
                     const int64_t o = (int64_t)(grow[valid ? J : 0] + sp) * a.ld + col;
                     zm[uu] = f4{0.f, 0.f, 0.f, 0.f};
                     ft[uu] = valid && first_touch(ijk[J], a.p, a.px, a.py, a.pz, accum);
                     if (valid) {
                         // the read-back, or Z_k (the input block) at a first touch
                         const cf *src = ft[uu] ? reinterpret_cast<const cf *>(a.X) + o : Y + o;
-                        old[uu] = load_pair(src, even_ld, col + 1 < a.nvec);
+                        old[uu] = load_pair(src, even_ld, two);
                     }
                     if (ft[uu]) {
-                        if (ep.Zkm)
-                            zm[uu] = load_pair(reinterpret_cast<const cf *>(ep.Zkm) + o, even_ld, col + 1 < a.nvec);
+                        if (ep.Zkm) zm[uu] = load_pair(reinterpret_cast<const cf *>(ep.Zkm) + o, even_ld, two);
                         const cd *R = ep.R + (int64_t)(grow[J] + sp) * ep.ldr + col;
-                        const cd r0 = R[0], r1 = col + 1 < a.nvec ? R[1] : cd{0.0, 0.0};
+                        const cd r0 = R[0], r1 = two ? R[1] : cd{0.0, 0.0};
                         rr[uu][0] = r0.x; rr[uu][1] = r0.y; rr[uu][2] = r1.x; rr[uu][3] = r1.y;
                     }
                 }
             }
+            // all of the group's results are formed before its first store:
+            // a store's data registers may not be overwritten by an ALU or
+            // LDS instruction before the store has completed, so forming the
+            // next piece in the registers of the previous one's store would
+            // wait for that store's round trip, piece by piece
+            f4 nv[PG];
 #pragma unroll
             for (int uu = 0; uu < PG; ++uu) {
-                const int c = tid + (u0 + uu) * kBfThreads;
-                const int J = c / VR, rem = c - J * VR, sp = rem / (VR / 2), q = rem - sp * (VR / 2);
-                const int64_t col = vb * VB + r * VR + 2 * q;
-                if (u0 + uu >= PIT || c >= PIECES || J >= a.n || col >= a.nvec) continue;
+                const int J = min(J0 + (u0 + uu) * (kBfThreads / VR), NP - 1);
                 if constexpr (EPI) {
                     if (ft[uu]) {
                         // beta Z_k + gamma Z_{k-1} + alpha lam R in double, rounded once
-                        const double l0 = a.alpha * ep.lam[col];
-                        const double l1 = col + 1 < a.nvec ? a.alpha * ep.lam[col + 1] : 0.0;
-                        const double lam4[4] = {l0, l0, l1, l1};
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
                             old[uu][i] = (float)(ep.beta * (double)old[uu][i] + ep.gamma * (double)zm[uu][i] +
-                                                 lam4[i] * rr[uu][i]);
+                                                 a.alpha * lam2[i >> 1] * rr[uu][i]);
                     }
                 }
                 const f4 yv = *reinterpret_cast<const f4 *>(ob + J * OS + sp * 2 * VR + 4 * q);
-                const f4 nv = f4{al * yv[0] + old[uu][0], al * yv[1] + old[uu][1], al * yv[2] + old[uu][2],
-                                 al * yv[3] + old[uu][3]};
+                nv[uu] = f4{al * yv[0] + old[uu][0], al * yv[1] + old[uu][1], al * yv[2] + old[uu][2],
+                            al * yv[3] + old[uu][3]};
+            }
+#pragma unroll
+            for (int uu = 0; uu < PG; ++uu) asm volatile("" : "+v"(nv[uu]));
+#pragma unroll
+            for (int uu = 0; uu < PG; ++uu) {
+                const int J = J0 + (u0 + uu) * (kBfThreads / VR);
+                if (u0 + uu >= PIT || J >= a.n || !colok) continue;
                 cf *dst = Y + (int64_t)(grow[J] + sp) * a.ld + col;
-                if (even_ld && col + 1 < a.nvec) {
-                    *reinterpret_cast<f4 *>(dst) = nv;
+                if (wide) {
+                    *reinterpret_cast<f4 *>(dst) = nv[uu];
                 } else {
-                    dst[0] = cf{nv[0], nv[1]};
-                    if (col + 1 < a.nvec) dst[1] = cf{nv[2], nv[3]};
+                    dst[0] = cf{nv[uu][0], nv[uu][1]};
+                    if (two) dst[1] = cf{nv[uu][2], nv[uu][3]};
                 }
             }
         }
