@@ -14,6 +14,8 @@
 #include <string>
 #include <vector>
 
+#include <rocsolver/rocsolver.h>
+
 #include "internal.h"
 
 using namespace chfsi;
@@ -631,18 +633,37 @@ int orthonormalize_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64
     return CHFSI_OK;
 }
 
+// Eigenpairs of the N x N Hermitian matrix A (row-major, overwritten): w the
+// eigenvalues in ascending order, Q (row-major) the eigenvectors as columns
+// (Algorithm RChFSI, the subspace eigenproblem of the RR step; the paper
+// solves it with ELPA).  rocSOLVER's divide and conquer (zheevd) works on the
+// column-major view of the buffer, conj(A); launch_conj_transpose turns its
+// eigenvectors into A's.  Synchronizes to read rocSOLVER's status.
+int herm_eig(chfsi_ctx *c, int N, cd *A, cd *Q, double *w, hipStream_t s) {
+    double *E = c->S<double>(c->L.red);
+    int *info = reinterpret_cast<int *>(E + N);
+    BLASCHK(c, rocblas_set_stream(c->blas, s));
+    BLASCHK(c, rocsolver_zheevd(c->blas, rocblas_evect_original, rocblas_fill_upper, N,
+                                reinterpret_cast<rocblas_double_complex *>(A), N, w, E, info));
+    HIPCHK(c, launch_conj_transpose(N, A, Q, s));
+    int h = 0;
+    HIPCHK(c, hipMemcpyAsync(&h, info, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (h != 0)
+        return fail(c, CHFSI_E_DEVICE, "subspace eigensolver (rocsolver_zheevd) failed, info = " + std::to_string(h));
+    return CHFSI_OK;
+}
+
 int rr_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t ld, double *ritz, cd *R,
             double *resnorm, hipStream_t s) {
     const Layout &L = c->L;
     cd *Hs = c->S<cd>(L.small);
     const size_t st = L.small_bytes / sizeof(cd);
-    cd *A2 = Hs + 2 * st, *V = Hs + 3 * st, *V2 = Hs + 4 * st;
+    cd *Q = Hs + 2 * st;
     int rc = gram(c, Y, HY, nvec, ld, Hs, s);
     if (rc) return rc;
     HIPCHK(c, launch_hermitize((int)nvec, Hs, s));
-    cd *Q = nullptr;
-    int sweeps = 0;
-    HIPCHK(c, launch_jacobi_eig((int)nvec, Hs, A2, V, V2, ritz, c->S<double>(L.red), 60, s, &sweeps, &Q));
+    if ((rc = herm_eig(c, (int)nvec, Hs, Q, ritz, s))) return rc;
     if ((rc = rotate(c, Y, Q, nvec, ld, s))) return rc;
     if ((rc = rotate(c, HY, Q, nvec, ld, s))) return rc;
     if ((rc = rotate(c, MY, Q, nvec, ld, s))) return rc;
@@ -662,7 +683,7 @@ int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t l
     const Layout &L = c->L;
     const size_t st = L.small_bytes / sizeof(cd);
     cd *Sm = c->S<cd>(L.small), *Hs = Sm + st, *T = Sm + 2 * st, *W = Sm + 3 * st, *Cm = Sm + 4 * st;
-    cd *A2 = Sm + 5 * st, *V = Sm + 6 * st, *V2 = Sm + 7 * st;
+    cd *A2 = Sm + 5 * st, *Q = Sm + 6 * st;
     double *scale = reinterpret_cast<double *>(c->scr + L.small + 9 * L.small_bytes);
     int *flag = c->S<int>(L.flag);
     int rc;
@@ -678,9 +699,7 @@ int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t l
     if ((rc = small_mm(c, Hs, T, W, nvec, false, s))) return rc;   // W = Hs T
     if ((rc = small_mm(c, T, W, Cm, nvec, true, s))) return rc;    // C = T^H W
     HIPCHK(c, launch_hermitize((int)nvec, Cm, s));
-    cd *Q = nullptr;
-    int sweeps = 0;
-    HIPCHK(c, launch_jacobi_eig((int)nvec, Cm, A2, V, V2, ritz, c->S<double>(L.red), 60, s, &sweeps, &Q));
+    if ((rc = herm_eig(c, (int)nvec, Cm, Q, ritz, s))) return rc;
     if ((rc = small_mm(c, T, Q, W, nvec, false, s))) return rc;    // W = T Q
     if (mixed_sr) {
         if ((rc = rotate_mixed(c, Y, W, nvec, ld, reinterpret_cast<cf *>(A2), s))) return rc;

@@ -200,7 +200,6 @@ hipError_t launch_cheb_last_dot(int64_t n, bool first, double c1, double c2, con
 hipError_t launch_splitmix(int64_t n, uint64_t seed, double *v, hipStream_t s);
 hipError_t launch_sqrt(int64_t n, const double *x, double *y, hipStream_t s);
 
-hipError_t launch_jacobi_eig(int N, cd *A, cd *A2, cd *V, cd *V2, double *w, double *red,
-                             int max_sweeps, hipStream_t s, int *sweeps_out, cd **Vout);
+hipError_t launch_conj_transpose(int N, const cd *Z, cd *Q, hipStream_t s);
 
 }  // namespace chfsi
