@@ -26,6 +26,8 @@
 // parity classes of cells are launched one after another, so no two
 // workgroups of a launch touch the same node and no atomics are needed
 // (results are deterministic).
+#include <type_traits>
+
 #include "cell_common.h"
 
 namespace chfsi {
@@ -157,6 +159,12 @@ __device__ __forceinline__ void mfma_panel(typename MM<T>::acc *acc, const T *as
     }
 }
 
+// 32 zero bytes: the source of the assembly's loads that need no data.  In
+// the global address space like the blocks (not const, which would place it
+// in the constant space and turn the selected loads into flat loads, whose
+// completion the LDS counter also waits for); never written.
+__device__ double kZeroPiece[4] = {0.0, 0.0, 0.0, 0.0};
+
 // One workgroup per (cell, VB = 4 MT vectors): its waves split the 16 MT
 // rows x NP columns of the block MT (16-row tiles) x WN (column groups of
 // NTW 16-column tiles).
@@ -248,58 +256,91 @@ __global__ __launch_bounds__(kCellThreads) void cell_kernel(CellParams a, EpiArg
         mfma_panel<T, NTW, NP, XS>(y, xs, reinterpret_cast<const T *>(a.Bphi), m, nt0, lane);
     }
 
-    // colour-ordered assembly: the previous values of all the lane's nodes
-    // are loaded before any is written back.  With FLAG_EPI the first touch
-    // of a node adds the filter step's recurrence terms instead, beta Z_k +
-    // gamma Z_{k-1} + alpha lam R, formed in double from Z_k (the input
-    // block), Z_{k-1} (which the output may overwrite: it is read first) and R.
+    // colour-ordered assembly.  Each lane owns one column and, per column
+    // tile t, one node (both spin rows).  The loads of a group of tiles are
+    // all issued before the first is used: a read-back where an earlier
+    // colour wrote the node, or (FLAG_EPI, at the node's first touch) Z_k,
+    // Z_{k-1} and R, from which beta Z_k + gamma Z_{k-1} + alpha lam R is
+    // formed in double (Z_{k-1} may be the output buffer: it is read first).
+    // Every register a load writes is zeroed before the loads, so no load
+    // waits on another path's write of its register.  The group's results
+    // are all formed before its first store, because a store's data
+    // registers cannot be rewritten until the store has completed.  Without
+    // FLAG_EPI one group covers all tiles; with it, the loads of EPG tiles.
     TC *Y = reinterpret_cast<TC *>(a.Y);
     const int64_t col = vb * VB + 4 * m + (lane >> 4);
     if (col < a.nvec) {
         const T al = (T)a.alpha;
         const bool accum = (a.flags & FLAG_ACCUM) != 0, epi = (a.flags & FLAG_EPI) != 0;
         const TC *Zk = reinterpret_cast<const TC *>(a.X), *Zkm = reinterpret_cast<const TC *>(ep.Zkm);
-        const cd *R = ep.R;
+        constexpr int EPG = sizeof(T) == 8 ? 4 : 6;
         const double dl = epi ? a.alpha * ep.lam[col] : 0.0;
-        int64_t off[NTW];
-        TC o0[NTW], o1[NTW];
+        // pieces that need no load read this zero piece instead (it stays
+        // in cache), so every load is unconditional and no loaded register
+        // has to be merged with a zero from another path
+        const TC *zc = reinterpret_cast<const TC *>(kZeroPiece);
+        const cd *zd = reinterpret_cast<const cd *>(kZeroPiece);
+        auto group = [&](auto epi_c, auto g_c, int t0) {
+            constexpr bool EPI = decltype(epi_c)::value;
+            constexpr int G = decltype(g_c)::value;
+            TC o0[G], o1[G];
+            [[maybe_unused]] TC m0[EPI ? G : 1], m1[EPI ? G : 1];
+            [[maybe_unused]] cd r0[EPI ? G : 1], r1[EPI ? G : 1];
+            bool ft[G], ok[G];
+            int64_t off[G];
 #pragma unroll
-        for (int t = 0; t < NTW; ++t) {
-            const int J = (nt0 + t) * 16 + (lane & 15);
-            off[t] = -1;
-            o0[t] = TC{0, 0};
-            o1[t] = TC{0, 0};
-            if (J < a.n) {
-                const int c = ijk[J];
-                const int64_t row = grow[J];
-                off[t] = row * a.ld + col;
-                if (!first_touch(c, a.p, a.px, a.py, a.pz, accum)) {
-                    o0[t] = Y[off[t]];
-                    o1[t] = Y[off[t] + a.ld];
-                } else if (epi) {
-                    const TC k0 = Zk[off[t]], k1 = Zk[off[t] + a.ld];
-                    const cd r0 = R[row * ep.ldr + col], r1 = R[(row + 1) * ep.ldr + col];
-                    double e0x = dl * r0.x + ep.beta * (double)k0.x, e0y = dl * r0.y + ep.beta * (double)k0.y;
-                    double e1x = dl * r1.x + ep.beta * (double)k1.x, e1y = dl * r1.y + ep.beta * (double)k1.y;
-                    if (Zkm) {
-                        const TC m0 = Zkm[off[t]], m1 = Zkm[off[t] + a.ld];
-                        e0x += ep.gamma * (double)m0.x; e0y += ep.gamma * (double)m0.y;
-                        e1x += ep.gamma * (double)m1.x; e1y += ep.gamma * (double)m1.y;
-                    }
-                    o0[t] = TC{(T)e0x, (T)e0y};
-                    o1[t] = TC{(T)e1x, (T)e1y};
+            for (int g = 0; g < G; ++g) {
+                const int t = t0 + g;
+                const int J = (nt0 + t) * 16 + (lane & 15);
+                ok[g] = t < NTW && J < a.n;
+                const int Jc = ok[g] ? J : 0;
+                const int64_t row = grow[Jc];
+                off[g] = row * a.ld + col;
+                ft[g] = first_touch(ijk[Jc], a.p, a.px, a.py, a.pz, accum);
+                // the read-back, or Z_k at a first touch with FLAG_EPI
+                const bool rd = EPI ? ok[g] : ok[g] && !ft[g];
+                const TC *src = (EPI && ft[g]) ? Zk : Y;
+                o0[g] = *(rd ? src + off[g] : zc);
+                o1[g] = *(rd ? src + off[g] + a.ld : zc);
+                if constexpr (EPI) {
+                    const bool fe = ok[g] && ft[g];
+                    m0[g] = *(fe && Zkm ? Zkm + off[g] : zc);
+                    m1[g] = *(fe && Zkm ? Zkm + off[g] + a.ld : zc);
+                    r0[g] = *(fe ? ep.R + row * ep.ldr + col : zd);
+                    r1[g] = *(fe ? ep.R + (row + 1) * ep.ldr + col : zd);
                 }
             }
-        }
+            TC v0[G], v1[G];
 #pragma unroll
-        for (int t = 0; t < NTW; ++t) {
-            if (off[t] >= 0) {
-                TC v0, v1;
-                v0.x = al * y[t][0] + o0[t].x; v0.y = al * y[t][1] + o0[t].y;
-                v1.x = al * y[t][2] + o1[t].x; v1.y = al * y[t][3] + o1[t].y;
-                Y[off[t]] = v0;
-                Y[off[t] + a.ld] = v1;
+            for (int g = 0; g < G; ++g) {
+                const int t = t0 + g < NTW ? t0 + g : NTW - 1;
+                if constexpr (EPI) {
+                    if (ft[g]) {
+                        o0[g] = TC{(T)(dl * r0[g].x + ep.beta * (double)o0[g].x + ep.gamma * (double)m0[g].x),
+                                   (T)(dl * r0[g].y + ep.beta * (double)o0[g].y + ep.gamma * (double)m0[g].y)};
+                        o1[g] = TC{(T)(dl * r1[g].x + ep.beta * (double)o1[g].x + ep.gamma * (double)m1[g].x),
+                                   (T)(dl * r1[g].y + ep.beta * (double)o1[g].y + ep.gamma * (double)m1[g].y)};
+                    }
+                }
+                v0[g] = TC{al * y[t][0] + o0[g].x, al * y[t][1] + o0[g].y};
+                v1[g] = TC{al * y[t][2] + o1[g].x, al * y[t][3] + o1[g].y};
             }
+#pragma unroll
+            for (int g = 0; g < G; ++g) asm volatile("" : "+v"(v0[g].x), "+v"(v0[g].y), "+v"(v1[g].x), "+v"(v1[g].y));
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (ok[g]) {
+                    Y[off[g]] = v0[g];
+                    Y[off[g] + a.ld] = v1[g];
+                }
+            }
+        };
+        if (epi) {
+#pragma unroll
+            for (int t0 = 0; t0 < NTW; t0 += EPG)
+                group(std::true_type{}, std::integral_constant<int, EPG>{}, t0);
+        } else {
+            group(std::false_type{}, std::integral_constant<int, NTW>{}, 0);
         }
     }
 }
