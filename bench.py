@@ -417,6 +417,53 @@ def measured_traffic(prec, config, nvec):
     return 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_scale"] + rec["write_kib_per_launch"] * rec["write_scale"])
 
 
+def hellmann_feynman(op, p, cfg, prec="bf16", tol=1e-8, max_iter=400, h=1e-4, seed=7101):
+    """Hellmann-Feynman check on the medium problem: L = sum of the n_wanted
+    lowest Ritz values.  The adjoint with G = X (FP64 and FP32) gives dL/dV,
+    dL/dB at the quadrature points; central differences of L re-solved at
+    (V, B) +- h (dV, dB), each solve warm-started from the converged block,
+    give the same directional derivative."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30128_amd import autograd, synth
+    nw, nsub, q = cfg["n_wanted"], cfg["nsub"], cfg["cheb_degree"]
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, seed)[:, 0])
+    X = torch.from_numpy(synth.random_block(p.ndof, nsub, seed + 1)).cuda()
+    t0 = time.perf_counter()
+    out = op.solve(X, nw, q, prec=prec, tol=tol, max_iter=max_iter, v0=v0, rr_mode=2)
+    t_base = time.perf_counter() - t0
+    log(f"[bench] hf: base solve {out['iters']} iterations to {out['max_res']:.2e} in {t_base:.1f} s")
+    Xw = X[:, :nw].contiguous()
+    grads = {pr: autograd.eigsum_grad(op, Xw if pr == "fp64" else Xw.to(torch.complex64), prec=pr)
+             for pr in ("fp64", "fp32")}
+    del Xw
+    dV = torch.from_numpy(0.01 * synth.random_real(p.V.shape, seed + 2)).cuda()
+    dB = torch.from_numpy(0.01 * synth.random_real(p.B.shape, seed + 3)).cuda()
+    V0, B0 = torch.from_numpy(p.V).cuda(), torch.from_numpy(p.B).cuda()
+    sums, its = [], []
+    for sgn in (+1, -1):
+        op.set_fields(V0 + sgn * h * dV, B0 + sgn * h * dB)
+        Xs = X.clone()
+        o2 = op.solve(Xs, nw, q, prec=prec, tol=tol, max_iter=max_iter, v0=v0, rr_mode=2)
+        del Xs
+        log(f"[bench] hf: solve at {sgn:+d}h, {o2['iters']} iterations to {o2['max_res']:.2e}")
+        sums.append(float(np.sum(o2["eigvals"][:nw])))
+        its.append(o2["iters"])
+    op.set_fields(V0, B0)
+    fd = (sums[0] - sums[1]) / (2 * h)
+    res = {"shape": f"medium, {nw} wanted in {nsub} columns, Chebyshev degree {q}, {prec} filter, tol {tol}",
+           "base_iterations": out["iters"], "base_seconds": t_base,
+           "base_max_res": out["max_res"], "pm_iterations": its, "h": h, "fd": fd}
+    for pr, (dVg, dBg) in grads.items():
+        an = float((torch.sum(dVg.double() * dV) + torch.sum(dBg.double() * dB)).item())
+        res[f"adjoint_{pr}"] = an
+        res[f"rel_err_{pr}"] = abs(fd - an) / abs(an)
+    del X
+    torch.cuda.empty_cache()
+    return res
+
+
 def converge(op, p, cfg, precs, tol, max_iter, seed=7002, eig_file=None, rr_mode=1):
     """Runs Algorithm RChFSI to the tolerance in each precision from the same
     start block, one iteration per library call so that progress is printed,
@@ -479,6 +526,8 @@ def main():
     ap.add_argument("--no-fp64-iter", action="store_true")
     ap.add_argument("--converge", action="store_true",
                     help="instead of timing: solve to --tol in fp64, bf16 and fp32 and compare eigenvalues")
+    ap.add_argument("--hf", action="store_true",
+                    help="only the Hellmann-Feynman check: re-solved eigenvalue sums vs the adjoint")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=60)
     ap.add_argument("--precs", default="fp64,bf16,fp32", help="precisions of --converge")
@@ -546,6 +595,10 @@ def main():
     nsub, nhx, q = cfg["nsub"], cfg["nvec_hx"], cfg["cheb_degree"]
     op = binding.Chfsi(p, max_nvec=max(nsub, nhx))
     log("[bench] setup done")
+    if args.hf:
+        print(json.dumps({"hellmann_feynman": hellmann_feynman(op, p, cfg, prec=args.prec, tol=args.tol)}),
+              flush=True)
+        return
     if args.converge:
         print(json.dumps({"convergence": converge(op, p, cfg, args.precs.split(","), args.tol, args.max_iter,
                                                   eig_file=args.eig_file, rr_mode=args.rr_mode)}), flush=True)
