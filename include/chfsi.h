@@ -207,7 +207,9 @@ int chfsi_orthonormalize(chfsi_ctx *ctx, void *Y, void *HY, void *MY,
                          int64_t nvec, int64_t ld, void *stream);
 
 /* Rayleigh-Ritz on an M-orthonormal block (Algorithm RChFSI, RR step):
- * Hs = Y^H HY (Hermitian part), Hs Q = Q Lambda with ascending Lambda,
+ * Hs = Y^H HY (Hermitian part), Hs Q = Q Lambda with ascending Lambda
+ * (dense Hermitian eigensolve by rocSOLVER's divide and conquer; its
+ * workspace comes from the rocBLAS handle, and the call synchronizes),
  * Y <- Y Q, HY <- HY Q, MY <- MY Q.  ritz: double device [nvec] output.
  * If R != NULL: R = HY - MY diag(ritz) and resnorm[j] = ||R_j||_2 (double
  * device [nvec]; resnorm may be NULL). */

@@ -1,10 +1,8 @@
 // Small dense FP64 kernels of the Rayleigh-Ritz stage (matrices of the
 // subspace size N, row-major complex128): Hermitian equilibration, Cholesky
 // factorisation, the triangular inverse that turns a Cholesky factor into
-// the orthonormalizing transform, and the dense Hermitian eigensolve
-// (parallel cyclic Jacobi: every round rotates N/2 disjoint index pairs in a
-// round-robin order, reading the previous iterate and writing the next one,
-// so one launch per round has no intra-launch dependencies).
+// the orthonormalizing transform, and the conjugate transpose that brings
+// the dense eigensolver's column-major eigenvectors into this layout.
 #include <cmath>
 #include <vector>
 
