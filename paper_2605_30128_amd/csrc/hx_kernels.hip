@@ -169,7 +169,7 @@ __device__ double kZeroPiece[4] = {0.0, 0.0, 0.0, 0.0};
 // rows x NP columns of the block MT (16-row tiles) x WN (column groups of
 // NTW 16-column tiles).
 template <typename T, int MT, int NP>
-__global__ __launch_bounds__(kCellThreads) void cell_kernel(CellParams a, EpiArgs ep) {
+__global__ __launch_bounds__(kCellThreads, sizeof(T) == 4 && NP <= 352 ? 2 : 1) void cell_kernel(CellParams a, EpiArgs ep) {
     using TC = typename Cplx<T>::type;
     using acc_t = typename MM<T>::acc;
     constexpr int CB = 16 * MT, VB = 4 * MT;
@@ -941,11 +941,12 @@ hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int fla
                                                                       epi)));
     }
     if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s, epi);
-    // float: 16 vectors per workgroup, except at p = 7 where the two
-    // accumulator sets of 32 column tiles per wave would spill; there 8
-    // vectors per workgroup and two column groups of 16 tiles
-    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, NP == 512 ? 2 : 4, NP>(c, mode, flags, alpha, X, Y, nvec,
-                                                                                  ld, s, epi)));
+    // float: 8 vectors per workgroup (two column groups of tiles per row
+    // tile).  Up to p = 6 the block (46 KB of LDS) and at most 256 registers
+    // per lane let two workgroups share a CU, so one workgroup's gather and
+    // assembly overlap the other's MFMAs (16 vectors per workgroup, one per
+    // CU, took 89.5 against 82.7 ms per H X at p = 6)
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<float, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s, epi)));
 }
 
 // the projection of the bfloat16 path runs in float (complex64 blocks)
