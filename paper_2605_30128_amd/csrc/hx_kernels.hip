@@ -501,24 +501,45 @@ __device__ __forceinline__ void proj_pass_bf16(const ProjParams &a, const int *g
 #pragma unroll
     for (int u = 0; u < NB; ++u) acc[u] = pf4{0, 0, 0, 0};
     const int ngroups = (a.n + 7) >> 3;
-#pragma unroll 2
-    for (int g = 0; g < ngroups; ++g) {
-        pbf8 av;
+    // the x values of node group g+1 are loaded while group g is converted
+    // and multiplied; every load is unconditional (a lane past the block or
+    // the cell reads element 0, and its values are replaced by zero), so the
+    // loads of the next group need not wait for any branch
+    cf xn[4];
+    float fn[2];
+    bool okn[2];
+    auto load_group = [&](int g) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int I = 8 * g + 2 * kq + h;
-            cf xu{0.f, 0.f}, xd{0.f, 0.f};
-            if (cv && I < a.n) {
-                const int64_t r = 2 * (int64_t)gtab[I] * a.ld + col;
-                const float f = sc[I];
-                xu = X[r];
-                xd = X[r + a.ld];
-                xu.x *= f; xu.y *= f; xd.x *= f; xd.y *= f;
-            }
-            av[4 * h] = (__bf16)xu.x;
-            av[4 * h + 1] = (__bf16)xu.y;
-            av[4 * h + 2] = (__bf16)xd.x;
-            av[4 * h + 3] = (__bf16)xd.y;
+            okn[h] = cv && I < a.n;
+            const int64_t r = okn[h] ? 2 * (int64_t)gtab[I] * a.ld + col : 0;
+            fn[h] = okn[h] ? sc[I] : 0.f;
+            xn[2 * h] = X[r];
+            xn[2 * h + 1] = X[okn[h] ? r + a.ld : 0];
+        }
+    };
+    load_group(0);
+    for (int g = 0; g < ngroups; ++g) {
+        cf xc[4];
+        float fc[2];
+        bool okc[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xc[i] = xn[i];
+        fc[0] = fn[0];
+        fc[1] = fn[1];
+        okc[0] = okn[0];
+        okc[1] = okn[1];
+        if (g + 1 < ngroups) load_group(g + 1);
+        pbf8 av;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float f = fc[h];
+            const bool ok = okc[h];
+            av[4 * h] = (__bf16)(ok ? xc[2 * h].x * f : 0.f);
+            av[4 * h + 1] = (__bf16)(ok ? xc[2 * h].y * f : 0.f);
+            av[4 * h + 2] = (__bf16)(ok ? xc[2 * h + 1].x * f : 0.f);
+            av[4 * h + 3] = (__bf16)(ok ? xc[2 * h + 1].y * f : 0.f);
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
