@@ -16,7 +16,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libchfsi.so")
+# CHFSI_LIBRARY selects another build of the same library (e.g. a host-sanitizer build)
+LIB_PATH = os.environ.get("CHFSI_LIBRARY") or os.path.join(HERE, "libchfsi.so")
 
 FP64, FP32, BF16 = 0, 1, 2
 PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16, FP64: FP64, FP32: FP32, BF16: BF16}

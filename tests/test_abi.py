@@ -10,7 +10,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "chfsi.h")
-LIB = os.path.join(ROOT, "paper_2605_30128_amd", "libchfsi.so")
+LIB = os.environ.get("CHFSI_LIBRARY") or os.path.join(ROOT, "paper_2605_30128_amd", "libchfsi.so")
 
 
 def declared_functions():
