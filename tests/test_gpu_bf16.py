@@ -141,21 +141,23 @@ def test_rounded_input_whole_product(B, oracle_lib, prec, tol):
         assert err > ROUNDED_FLOOR
 
 
+@pytest.mark.parametrize("degree", [6, 7])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_hx_degree7_soc(B, oracle_lib, prec):
-    """p = 7 (512 nodes per cell, the slab's degree) in the reduced
-    precisions with spin-orbit on: whole product and, in bfloat16, the
-    field and spin-orbit terms separately."""
+def test_hx_high_degree_soc(B, oracle_lib, prec, degree):
+    """p = 6 and p = 7 (343 and 512 nodes per cell, the medium and slab
+    workloads' degrees, whose bfloat16 kernels use other wave tilings than
+    the tiny one) in the reduced precisions with spin-orbit on: whole
+    product and, in bfloat16, the field and spin-orbit terms separately."""
     o = oracle_lib
-    p = synth.make_problem(ncell=(2, 2, 2), box=(4.0, 4.0, 4.0), degree=7, nwells=2, natoms=2, nbeta=8,
-                           seed=207)
+    p = synth.make_problem(ncell=(2, 2, 2), box=(4.0, 4.0, 4.0), degree=degree, nwells=2, natoms=2, nbeta=8,
+                           seed=200 + degree)
     assert p.npairs > 0
-    X = synth.random_block(p.ndof, 24, 504)
+    X = synth.random_block(p.ndof, 24, 497 + degree)
     ref = o.Oracle(p).apply_H(X)
     op = B.Chfsi(p, max_nvec=24)
     Y = op.apply_H(_dev(X), prec=prec).cpu().numpy()
     err = _rel(Y, ref)
-    print(f"p=7 {prec} H X rel err {err:.3e}")
+    print(f"p={degree} {prec} H X rel err {err:.3e}")
     if prec == "fp32":
         assert err < 2e-6, err
         return
@@ -169,7 +171,7 @@ def test_hx_degree7_soc(B, oracle_lib, prec):
     pz = _no_fields(p)
     Y0n = B.Chfsi(_no_soc(pz), max_nvec=24).apply_H(Xd, prec="bf16").cpu().numpy()
     e_s = _rel(Y0 - Y0n, o.Oracle(pz).apply_H(X, flags=o.NLOC))
-    print(f"p=7 bf16 terms: field {e_f:.3e}, spin-orbit {e_s:.3e}")
+    print(f"p={degree} bf16 terms: field {e_f:.3e}, spin-orbit {e_s:.3e}")
     assert e_s < TERM_TOL, e_s
     # Y - Y0 = Phi^T (bf16(W Phi X + S) - bf16(S)): the spin-orbit part S
     # rounds with the field term, so the gate is on the pair difference
