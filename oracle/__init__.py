@@ -247,6 +247,41 @@ class Oracle:
             raise RuntimeError("filter failed")
         return Y
 
+    def filter_sampled(self, degree, bounds, X, ritz, R, nodes):
+        """The R-ChFSI filter (eq. rChFSIrecurrence with D^-1, recovery of
+        Algorithm RChFSI) at sampled nodes only: Y_q = D^-1 Z_q + X Lambda_q
+        on rows (2 node, 2 node + 1) of each node, as [node][spin][column].
+        Z_0 = 0, Z_1 = s_1 R / e; the products H D^-1 Z_k of steps
+        k < q - 1 are full ones, the last one (step q - 1) is evaluated at
+        the sampled nodes only, so a large mesh costs q - 2 full products
+        (the filter acts column by column: pass only the columns wanted)."""
+        X = _c(X, np.complex128); R = _c(R, np.complex128)
+        ritz = _c(ritz, np.float64); nodes = _c(nodes, np.int64)
+        lmin, lT, lmax = (float(b) for b in bounds)
+        c, e = 0.5 * (lmax + lT), 0.5 * (lmax - lT)
+        s1 = e / (lmin - c)
+        D = np.repeat(self.mass_diag(), 2)[:, None]          # one value per spinor row
+        rows = np.stack([2 * nodes, 2 * nodes + 1], axis=1)  # [node][spin]
+
+        Lkm, Lk = np.ones_like(ritz), s1 * (ritz - c) / e   # C_0, C_1 at the Ritz values
+        Zkm, Zk = np.zeros_like(R), s1 * R / e
+        sk = s1
+        for step in range(1, degree):
+            sn = 1.0 / (2.0 / s1 - sk)
+            a = 2.0 * sn / e
+            if step < degree - 1:
+                HW = self.apply_H(Zk / D)
+                Zn = a * (HW - c * Zk) - sk * sn * Zkm + a * R * Lk[None, :]
+            else:
+                HW = self.apply_H_sampled(Zk / D, nodes, np.arange(X.shape[1]))
+                Zn = (a * (HW - c * Zk[rows]) - sk * sn * Zkm[rows] + a * R[rows] * Lk[None, None, :])
+            Lkm, Lk = Lk, a * (ritz - c) * Lk - sk * sn * Lkm
+            Zkm, Zk = Zk, Zn
+            sk = sn
+        if degree == 1:
+            Zk = Zk[rows]
+        return Zk / D[rows] + X[rows] * Lk[None, None, :]
+
     def chebyshev_plain(self, degree, bounds, X, exactM=False):
         X = _c(X, np.complex128); bounds = _c(bounds, np.float64)
         Y = np.zeros_like(X)

@@ -1,0 +1,88 @@
+"""Parity of the R-ChFSI filter at the medium workload's full size, in the
+launch configuration of the timed iteration (16^3 cells, p = 6, 64 atoms x
+8 projectors, one block of 576 columns filtered in place, FP64 block in
+device memory), in FP64, FP32 and bfloat16.
+
+The filter runs q = 3 steps, so both recurrence paths of the fused kernels
+run (step 1 without Z_{k-1}, step 2 with it).  The oracle evaluates the
+same filter at sampled nodes (eq. rChFSIrecurrence, recovery of Algorithm
+RChFSI; its last product only at those nodes) on the sampled columns alone,
+which is exact because the filter acts column by column.  X and R are drawn
+on the device; the oracle receives the sampled columns.  Gates are on the
+largest sampled error relative to the largest sampled value, as in the
+medium H X test.  In bfloat16 they are on the filtered-residual part
+D^-1 Z_q = Y - X Lambda_q (Lambda_q = C_q(ritz) is formed in FP64): its
+norm over all samples within 1e-2 (two products of about 3.4e-3 rms
+relative error each, as on the small meshes) and its largest sampled error
+within 3e-2 (168 samples, so about three times the rms)."""
+import numpy as np
+import pytest
+
+from paper_2605_30128_amd import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+torch = pytest.importorskip("torch")
+
+NSUB = 576
+Q = 3
+COLS = np.array([0, 1, 31, 32, 287, 288, 575])
+BOUNDS = [-1.0, 2.0, 500.0]
+
+
+@pytest.fixture(scope="module")
+def medium_filter(oracle_lib):
+    from paper_2605_30128_amd import binding
+    binding.load()
+    p = synth.make_config("medium")
+    op = binding.Chfsi(p, max_nvec=NSUB)
+    n1, Nx = 7, 96
+    ex, ey, ez = 1000 % 16, (1000 // 16) % 16, 1000 // 256
+    nodes = []
+    for (i, j, k) in [(0, 0, 0), (6, 0, 0), (0, 6, 0), (6, 6, 6), (3, 0, 0), (3, 3, 0), (3, 3, 3), (1, 5, 2)]:
+        nodes.append((ex * 6 + i) % Nx + Nx * ((ey * 6 + j) % Nx + Nx * ((ez * 6 + k) % Nx)))
+    # a cell in the support of the first atom's projectors: corner and centre
+    ca = int(p.pair_cell[p.pair_ptr[0]])
+    ax, ay, az = ca % 16, (ca // 16) % 16, ca // 256
+    for (i, j, k) in [(0, 0, 0), (3, 3, 3)]:
+        nodes.append((ax * 6 + i) % Nx + Nx * ((ay * 6 + j) % Nx + Nx * ((az * 6 + k) % Nx)))
+    nodes += [0, p.nnodes - 1]
+    nodes = np.array(nodes)
+    print(f"medium filter: {p.ndof} dofs x {NSUB} columns, q = {Q}, {len(nodes)} nodes", flush=True)
+    X = synth.device_block(p.ndof, NSUB, 811)
+    R = synth.device_block(p.ndof, NSUB, 812)
+    ritz = np.linspace(BOUNDS[0], BOUNDS[1], NSUB)
+    ci = torch.from_numpy(COLS).cuda()
+    Xs, Rs = X[:, ci].cpu().numpy(), R[:, ci].cpu().numpy()
+    o = oracle_lib.Oracle(p)
+    ref = o.filter_sampled(Q, BOUNDS, Xs, ritz[COLS], Rs, nodes)
+    base = o.filter_sampled(Q, BOUNDS, Xs, ritz[COLS], np.zeros_like(Rs), nodes)
+    print("oracle samples done", flush=True)
+    return dict(p=p, op=op, X=X, R=R, ritz=ritz, nodes=nodes, ref=ref, base=base)
+
+
+def _sample(Y, nodes):
+    rows = torch.from_numpy(np.stack([2 * nodes, 2 * nodes + 1], axis=1).ravel()).cuda()
+    got = Y[rows][:, torch.from_numpy(COLS).cuda()].cpu().numpy()
+    return got.reshape(len(nodes), 2, len(COLS))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6), ("bf16", 3e-2)])
+def test_filter_medium_sampled(medium_filter, prec, tol):
+    m = medium_filter
+    print(f"filter medium {prec}", flush=True)
+    Y = m["X"].clone()
+    m["op"].filter(Y, torch.from_numpy(m["ritz"]), m["R"], Q, BOUNDS, prec=prec, Y=Y)  # in place, as in the solve
+    got = _sample(Y, m["nodes"])
+    del Y
+    torch.cuda.empty_cache()
+    if prec == "bf16":
+        z, zref = got - m["base"], m["ref"] - m["base"]
+        err = np.abs(z - zref).max() / np.abs(zref).max()
+        fro = np.linalg.norm(z - zref) / np.linalg.norm(zref)
+        print(f"  Z-part max rel err {err:.3e}, over all samples {fro:.3e}")
+        assert 1e-5 < fro < 1e-2, fro
+        assert err < tol, err
+        return
+    err = np.abs(got - m["ref"]).max() / np.abs(m["ref"]).max()
+    print(f"  max rel err {err:.3e}")
+    assert err < tol, err

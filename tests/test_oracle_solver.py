@@ -102,6 +102,32 @@ def test_rchfsi_with_exact_mass_equals_chfsi(oracle_lib):
     assert np.abs(Yd - Yc).max() > 1e-6 * np.abs(Yc).max()
 
 
+@pytest.mark.parametrize("q", [1, 2, 3, 5])
+def test_filter_sampled_matches_full_filter(oracle_lib, q):
+    """The sampled filter (a Python restatement of the recurrence whose last
+    product is evaluated at sampled nodes only) agrees with the C filter on
+    those nodes, on a random block with a random residual (two independent
+    codings of eq. rChFSIrecurrence and the recovery).  A sign or index slip
+    in either (a dropped Z_{k-1} term, R Lambda_k taken at the wrong step,
+    D in place of D^-1) shows up at q >= 3."""
+    p = _tiny(degree=3, ncell=(2, 2, 2))
+    o = oracle_lib.Oracle(p)
+    X = synth.random_block(p.ndof, 6, 71)
+    R = synth.random_block(p.ndof, 6, 72)
+    ritz = np.array([-0.4, -0.1, 0.2, 0.5, 0.9, 1.4])
+    bounds = [-0.5, 1.5, 80.0]
+    nodes = np.array([0, 1, 7, 30, p.nnodes // 2, p.nnodes - 1])
+    full = o.filter(q, bounds, X, ritz, R)
+    ref = np.stack([full[2 * nodes], full[2 * nodes + 1]], axis=1)
+    got = o.filter_sampled(q, bounds, X, ritz, R, nodes)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the residual terms matter: without R the result is X C_q(Lambda) alone
+    zero = o.filter_sampled(q, bounds, X, ritz, np.zeros_like(R), nodes)
+    assert np.abs(zero - ref).max() > 1e-3 * np.abs(ref).max()
+    assert np.abs(zero - np.stack([X[2 * nodes], X[2 * nodes + 1]], axis=1) * _cq(ritz, q, *bounds)).max() \
+        <= 1e-12 * np.abs(zero).max()
+
+
 def test_lanczos_upper_bound(oracle_lib):
     p = _tiny(degree=3)
     o = oracle_lib.Oracle(p)
