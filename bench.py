@@ -7,13 +7,15 @@ the double-precision residual.  `value` is the number of H X dof-vectors
 the timed steps processed per second (q products of the nsub-column block per
 iteration), i.e. whole-job H X throughput including the Rayleigh-Ritz stage.
 Isolated H X throughputs per precision, the double-precision iteration
-time, the roofline of the dominant kernel and the CPU oracle baseline are
-reported beside it, together with the block floating-point codec's
+time, the roofline of the dominant kernel (`roofline`: the filter's fused
+cell kernel, timed with device events inside the timed iterations; the plain
+H X kernel's is `roofline_hx`) and the CPU oracle baseline are reported
+beside it, together with the block floating-point codec's
 throughput and the Poisson workload (matrix-free K x throughput with its
 roofline, PCG time to an absolute residual of 1e-10).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec bf16|fp32]
-python bench.py --poisson-only | --slab-only | --hx-only | --converge [--precs fp64,bf16,fp32]
+python bench.py --poisson-only | --slab-only | --hx-only | --iter-only | --converge [--precs fp64,bf16,fp32]
 """
 from __future__ import annotations
 
@@ -178,6 +180,40 @@ def cell_roofline(p, prec, nvec, ms_cell, launches, config):
     roof["flops_per_launch"] = flops_launch
     roof["bytes_per_launch"] = bytes_launch
     roof["ms_per_launch"] = t_launch * 1e3
+    return roof
+
+
+def filter_roofline(p, prec, nsub, degree, iters, t_cell, launches, config):
+    """Roofline of the filter's cell-operator kernel (the fused recurrence
+    variant, the dominant kernel of an R-ChFSI iteration) from device events
+    around its launches inside the timed iterations.  Algorithmic work per
+    filter step: the H D^-1 Z_k flops (local plus the apply half of the
+    spin-orbit term) and the bytes of reading Z_k, Z_{k-1} (from the second
+    step on) and R (complex128) and writing Z_{k+1} once: 40 B per dof and
+    vector in FP32/BF16 (32 B in the first step), 64 B in FP64."""
+    loc, nl = hx_flops(p, nsub)
+    cz = CSIZE[prec]
+    nsteps = iters * (degree - 1)
+    flops = nsteps * (loc + nl / 2)
+    per_dof = (degree - 2) * (3 * cz + 16) + (2 * cz + 16)  # per dof and vector, one filter
+    bytes_ = iters * p.ndof * nsub * per_dof
+    t_launch = t_cell / launches
+    flops_launch, bytes_launch = flops / launches, bytes_ / launches
+    if flops_launch / PEAK[prec] >= bytes_launch / PEAK["hbm"]:
+        roof = {"bound": "mfma", "achieved": flops_launch / t_launch / 1e12, "peak": PEAK[prec] / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_launch / t_launch / 1e9, "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(prec, config, nsub, variant="epi")
+    roof["kernel"] = (f"cell_kernel ({prec}, fused recurrence), the filter's product in the timed iterations: "
+                      f"{launches} launches ({nsteps} steps x colours), {nsub} columns")
+    roof["flops_per_launch"] = flops_launch
+    roof["bytes_per_launch"] = bytes_launch
+    roof["ms_per_launch"] = t_launch * 1e3
+    roof["frac_mfma"] = flops_launch / t_launch / PEAK[prec]
+    roof["frac_hbm"] = bytes_launch / t_launch / PEAK["hbm"]
     return roof
 
 
@@ -398,13 +434,14 @@ def kx_traffic(config):
     return None
 
 
-def measured_traffic(prec, config, nvec):
+def measured_traffic(prec, config, nvec, variant=""):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE runs, calibrated), or None when the
     summary is for another workload or the kernel source has changed since
     the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"cell_kernel_{prec}_{config}_counters.txt")
+    tag = f"{prec}_{variant}" if variant else prec
+    path = os.path.join(ROOT, "profiles", f"cell_kernel_{tag}_{config}_counters.txt")
     if not os.path.exists(path):
         return None
     rec = None
@@ -551,6 +588,9 @@ def main():
     ap.add_argument("--poisson-only", action="store_true", help="run only the Poisson leg")
     ap.add_argument("--no-pcg", action="store_true", help="Poisson leg: K x only")
     ap.add_argument("--kx-reps", type=int, default=50)
+    ap.add_argument("--iter-only", action="store_true",
+                    help="only the warm-up and timed R-ChFSI iterations (after the 1 GiB fill and sum that "
+                         "calibrate the memory counters)")
     ap.add_argument("--calibrate", action="store_true",
                     help="with --poisson-only: run the 1 GiB fill and sum used to scale memory counters")
     args = ap.parse_args()
@@ -607,7 +647,7 @@ def main():
                                                   eig_file=args.eig_file, rr_mode=args.rr_mode)}), flush=True)
         return
 
-    if args.hx_only:
+    if args.hx_only or args.iter_only:
         # memory-counter calibration: a fill writes 2^30 bytes, a sum reads them
         a = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
         a.fill_(1.0)
@@ -618,7 +658,7 @@ def main():
     # ---- isolated H X per precision (nhx vectors)
     hx = {}
     prof = {}
-    for prec in args.hx_precs.split(","):
+    for prec in [] if args.iter_only else args.hx_precs.split(","):
         dt = torch.complex128 if prec == "fp64" else torch.complex64
         X = torch.from_numpy(synth.random_block(p.ndof, nhx, 7001)).to("cuda", dt)
         Y = torch.empty_like(X)
@@ -651,13 +691,20 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = op.solve(X, n_wanted, q, prec=args.prec, max_iter=args.steps, fixed_iters=True, resume=True, work=work,
-                   lambda_max=lmax, rr_mode=args.rr_mode)
+                   lambda_max=lmax, rr_mode=args.rr_mode, profile=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall / args.steps * 1e3
     value = args.steps * q * p.ndof * nsub / wall / 1e9
     log(f"[bench] {args.steps} {args.prec} iterations: {ms_step:.1f} ms/iter (filter {out['t_filter']:.3f}s, "
         f"rr {out['t_rr']:.3f}s), residual {out['max_res']:.3e}")
+    roof = filter_roofline(p, args.prec, nsub, q, out["iters"], out["t_filter_cell"], out["filter_cell_launches"],
+                           args.config)
+    log(f"[bench] filter cell kernel: {roof['ms_per_launch']:.3f} ms per launch, {roof['frac']:.3f} of the "
+        f"{roof['bound']} roof (mfma {roof['frac_mfma']:.3f}, hbm {roof['frac_hbm']:.3f})")
+    if args.iter_only:
+        print(json.dumps({"sec_per_iter": {args.prec: ms_step / 1e3}, "roofline": roof}), flush=True)
+        return
     it64 = None
     if not args.no_fp64_iter and args.prec != "fp64":
         torch.cuda.synchronize()
@@ -679,9 +726,9 @@ def main():
     del X, work, out
     torch.cuda.empty_cache()
 
-    # ---- roofline of the dominant kernel: the cell operator in the step's precision
+    # ---- roofline of the plain H X cell kernel (the timed iterations' fused kernel is `roof`)
     pr = args.prec
-    roof = cell_roofline(p, pr, nhx, prof[pr]["ms_cell"], prof[pr]["launches"], args.config)
+    roof_hx = cell_roofline(p, pr, nhx, prof[pr]["ms_cell"], prof[pr]["launches"], args.config)
 
     bfp = bfp_throughput()
     log(f"[bench] bfp codec: " + ", ".join(f"{k} enc {v['encode_GBps']:.0f} / dec {v['decode_GBps']:.0f} GB/s"
@@ -738,6 +785,7 @@ def main():
         "hx_gdofvec_per_s": hx,
         "hx_profile_ms": prof,
         "roofline": roof,
+        "roofline_hx": roof_hx,
         "bfp_codec": bfp,
         "poisson": poi,
         "cpu_baseline": cpu,

@@ -270,6 +270,11 @@ typedef struct {
                            Sec. III-C4); 0: min(nsub, filter_block).  The
                            filter is column-wise, so blocking changes no
                            result */
+    int profile;        /* if != 0, device events on `stream` around the cell-
+                           operator launches of every filter step (one pair
+                           per step and column block) fill
+                           report->t_filter_cell and
+                           report->filter_cell_launches; 0: both stay 0 */
 } chfsi_solve_opts;
 
 typedef struct {
@@ -279,6 +284,10 @@ typedef struct {
     double lambda_bounds[3];/* last lmin, lT, lmax */
     double t_filter, t_rr, t_total; /* seconds (device events), summed */
     double t_iter_median;   /* median seconds per iteration from the 2nd on */
+    double t_filter_cell;   /* with opts.profile: seconds in the filter steps'
+                               cell-operator launches (device events), summed */
+    int64_t filter_cell_launches; /* with opts.profile: number of those
+                               launches (one per non-empty cell colour and step) */
 } chfsi_report;
 
 /* Workspace bytes chfsi_solve needs for nsub columns with leading dim ld. */

@@ -44,7 +44,7 @@ class _Proj(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("prec", C.c_int), ("degree", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("lanczos_steps", C.c_int), ("lambda_max", C.c_double), ("fixed_iters", C.c_int),
-                ("rr_mode", C.c_int), ("resume", C.c_int), ("block", C.c_int64)]
+                ("rr_mode", C.c_int), ("resume", C.c_int), ("block", C.c_int64), ("profile", C.c_int)]
 
 
 class PlanOpts(C.Structure):
@@ -54,7 +54,8 @@ class PlanOpts(C.Structure):
 class Report(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("max_res", C.c_double),
                 ("lambda_bounds", C.c_double * 3), ("t_filter", C.c_double), ("t_rr", C.c_double),
-                ("t_total", C.c_double), ("t_iter_median", C.c_double)]
+                ("t_total", C.c_double), ("t_iter_median", C.c_double), ("t_filter_cell", C.c_double),
+                ("filter_cell_launches", C.c_int64)]
 
 
 class PcgOpts(C.Structure):
@@ -384,10 +385,12 @@ class Chfsi:
 
     def solve(self, X, n_wanted, degree, prec="fp64", tol=1e-8, max_iter=100, v0=None,
               lanczos_steps=20, lambda_max=0.0, fixed_iters=False, resume=False, work=None, rr_mode=1,
-              block=0):
+              block=0, profile=False):
         """Algorithm RChFSI from the start block X (overwritten with Ritz vectors).
         resume=True continues from the state a previous call left in X and
-        `work` (returned as out['work']); lambda_max must then be given."""
+        `work` (returned as out['work']); lambda_max must then be given.
+        profile=True also times the filter steps' cell-operator launches
+        (out['t_filter_cell'] seconds over out['filter_cell_launches'])."""
         ld = self._block(X, torch.complex128, "X")
         nsub = ld
         ws = C.c_size_t()
@@ -398,7 +401,7 @@ class Chfsi:
             work = torch.empty(ws.value, dtype=torch.uint8, device=X.device)
         opts = SolveOpts(PREC[prec], int(degree), float(tol), int(max_iter),
                          int(lanczos_steps if v0 is not None else 0), float(lambda_max), int(fixed_iters),
-                         int(rr_mode), int(resume), int(block))
+                         int(rr_mode), int(resume), int(block), int(bool(profile)))
         eig = np.zeros(n_wanted)
         hist = np.zeros(max_iter + 2)
         rep = Report()
@@ -411,4 +414,5 @@ class Chfsi:
         return dict(status=rc, eigvals=eig, iters=rep.iters, converged=bool(rep.converged),
                     max_res=rep.max_res, hist_res=hist[:rep.iters + 1], bounds=list(rep.lambda_bounds),
                     t_filter=rep.t_filter, t_rr=rep.t_rr, t_total=rep.t_total,
-                    t_iter_median=rep.t_iter_median, work=work)
+                    t_iter_median=rep.t_iter_median, t_filter_cell=rep.t_filter_cell,
+                    filter_cell_launches=rep.filter_cell_launches, work=work)

@@ -729,8 +729,21 @@ int rr_general_impl(chfsi_ctx *c, cd *Y, cd *HY, cd *MY, int64_t nvec, int64_t l
     return CHFSI_OK;
 }
 
+// Device events around the cell-operator launches of filter steps: pairs
+// (start, end) recorded on the filter's stream, read after the caller's
+// synchronization.  A step is timed only while the pool has room for its pair.
+struct StepEvents {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    ~StepEvents() {
+        for (auto e : ev)
+            if (e) hipEventDestroy(e);
+    }
+};
+
 int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds, const cd *X,
-                const double *ritz, const cd *R, cd *Y, int64_t nvec, int64_t ld, hipStream_t s) {
+                const double *ritz, const cd *R, cd *Y, int64_t nvec, int64_t ld, hipStream_t s,
+                StepEvents *pe = nullptr) {
     const Layout &L = c->L;
     const double lmin = bounds[0], lT = bounds[1], lmax = bounds[2];
     const double cc = 0.5 * (lmax + lT), e = 0.5 * (lmax - lT);
@@ -765,7 +778,13 @@ int filter_impl(chfsi_ctx *c, chfsi_prec prec, int degree, const double *bounds,
         // operator: the first colour to reach a node writes all four terms, later colours add a H D^{-1} Z_k
         if (nl) HIPCHK(c, launch_nonlocal_coeffs(c, prec, FLAG_DINV, Zc, nvec, nvec, s));
         const EpiArgs ep{Zp, R, ld, lamk + (int64_t)k * nvec, -a * cc, -sk * sn};
+        const bool timed = pe && pe->used + 2 <= pe->ev.size();
+        if (timed) HIPCHK(c, hipEventRecord(pe->ev[pe->used], s));
         HIPCHK(c, launch_cell_op(c, prec, MODE_HAM, FLAG_EPI | FLAG_DINV | nl, a, Zc, Zn, nvec, nvec, s, &ep));
+        if (timed) {
+            HIPCHK(c, hipEventRecord(pe->ev[pe->used + 1], s));
+            pe->used += 2;
+        }
         Zp = Zc;
         Zc = Zn;
         sk = sn;
@@ -1188,6 +1207,16 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
     } evs;
     hipEvent_t *ev = evs.ev;
     for (int i = 0; i < 4; ++i) HIPCHK(c, hipEventCreate(&ev[i]));
+    // with opts.profile: a (start, end) pair per filter step and column block
+    StepEvents steps;
+    if (o->profile) {
+        steps.ev.resize((size_t)2 * (o->degree - 1) * (size_t)((nsub + nb - 1) / nb), nullptr);
+        for (auto &e : steps.ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    int ncolour = 0;
+    for (int col = 0; col < 8; ++col) ncolour += c->colour_ptr[col + 1] > c->colour_ptr[col];
+    double t_cell = 0;
+    int64_t n_cell = 0;
     HIPCHK(c, hipEventRecord(ev[0], s));
     if (!o->resume) {
         if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) return rc;
@@ -1228,7 +1257,7 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
         rc = CHFSI_OK;
         for (int64_t b0 = 0; b0 < nsub && !rc; b0 += nb)
             rc = filter_impl(c, o->prec, o->degree, bounds, X + b0, ritz + b0, R + b0, X + b0,
-                             std::min(nb, nsub - b0), ld, s);
+                             std::min(nb, nsub - b0), ld, s, o->profile ? &steps : nullptr);
         if (rc) { status = rc; break; }
         HIPCHK(c, hipEventRecord(ev[2], s));
         if ((rc = apply_H_impl(c, CHFSI_FP64, X, HX, nsub, ld, s))) { status = rc; break; }
@@ -1246,6 +1275,13 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
         float ms1 = 0, ms2 = 0;
         hipEventElapsedTime(&ms1, ev[1], ev[2]);
         hipEventElapsedTime(&ms2, ev[2], ev[3]);
+        for (size_t i = 0; i + 1 < steps.used; i += 2) {
+            float m = 0;
+            HIPCHK(c, hipEventElapsedTime(&m, steps.ev[i], steps.ev[i + 1]));
+            t_cell += m * 1e-3;
+            n_cell += ncolour;
+        }
+        steps.used = 0;
         t_filter += ms1 * 1e-3;
         t_rr += ms2 * 1e-3;
         titer.push_back((ms1 + ms2) * 1e-3);
@@ -1265,6 +1301,8 @@ int chfsi_solve(chfsi_ctx *c, int64_t n_wanted, const chfsi_solve_opts *o, void 
         rep->t_filter = t_filter;
         rep->t_rr = t_rr;
         rep->t_total = mst * 1e-3;
+        rep->t_filter_cell = t_cell;
+        rep->filter_cell_launches = n_cell;
         std::vector<double> tt(titer.size() > 1 ? titer.begin() + 1 : titer.begin(), titer.end());
         std::sort(tt.begin(), tt.end());
         rep->t_iter_median = tt.empty() ? 0 : tt[tt.size() / 2];

@@ -209,6 +209,28 @@ def test_solve_blocked_filter_matches(B):
     assert np.array_equal(Xs[0], Xs[1])
 
 
+def test_solve_profile_filter_cell_launches(B):
+    """opts.profile times the filter's cell-operator launches with device
+    events and changes no result: one (start, end) pair per filter step and
+    column block, eight colour launches each on the 4x4x4-cell mesh."""
+    p = synth.make_config("tiny")
+    op = B.Chfsi(p, max_nvec=40)
+    X0 = synth.random_block(p.ndof, 40, 2201)
+    v0 = torch.from_numpy(synth.random_block(p.ndof, 1, 2202)[:, 0])
+    q, outs, Xs = 12, [], []
+    for profile in (False, True):
+        X = _dev(X0)
+        outs.append(op.solve(X, 32, q, prec="bf16", tol=1e-8, max_iter=4, v0=v0, block=16, rr_mode=2,
+                             fixed_iters=True, profile=profile))
+        Xs.append(X.cpu().numpy())
+    assert np.array_equal(Xs[0], Xs[1]) and np.array_equal(outs[0]["eigvals"], outs[1]["eigvals"])
+    assert outs[0]["filter_cell_launches"] == 0 and outs[0]["t_filter_cell"] == 0
+    o = outs[1]
+    assert o["iters"] == 4
+    assert o["filter_cell_launches"] == o["iters"] * (q - 1) * 3 * 8
+    assert 0 < o["t_filter_cell"] < o["t_filter"]
+
+
 def test_plan_for_reduced_precision_filter(B, tiny_state):
     """A scratch planned for complex64 recurrence blocks (filter_prec bf16)
     runs the bfloat16 filter at full width and an FP64 filter up to half of
