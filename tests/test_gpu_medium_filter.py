@@ -11,17 +11,15 @@ which is exact because the filter acts column by column.  X and R are drawn
 on the device; the oracle receives the sampled columns.  Gates are on the
 largest sampled error relative to the largest sampled value, as in the
 medium H X test.  In bfloat16 they are on the filtered-residual part
-D^-1 Z_q = Y - X Lambda_q (Lambda_q = C_q(ritz) is formed in FP64), whose
-rounding error is larger on a random block than for a Ritz residual: the
-mid-spectrum components of a random block nearly cancel in (H D^-1 - c) Z,
-so the relative error is about three times that of the small-mesh filter
-tests (measured 1.1e-2 over the 168 samples, 1.3e-2 at the worst one).  The
-gates, 3e-2 over the samples and 5e-2 at the worst one, catch gross errors
-of the full-size launches (a dropped Z_{k-1} term moves the result by 0.73);
-the finer mistakes (R Lambda_k at the wrong step, 2.7e-2 there) are caught by
-the p = 6 and 7 filter tests, whose gate is 1e-2, and the field and
-spin-orbit terms, which a random block hides here (4e-4 and 2e-7), by the
-term tests."""
+D^-1 Z_q = Y - X Lambda_q (Lambda_q = C_q(ritz) is formed in FP64).  Its
+rounding error on a random block is about twice that of the small-mesh
+filter tests, since the block's mid-spectrum components nearly cancel in
+(H D^-1 - c) Z: measured 6.3e-3 over the 168 samples and 8.2e-3 at the
+worst one.  The gates are 1.5e-2 and 3e-2.  In the oracle, on a block of
+the same kind, taking R Lambda_k at the wrong step moves the result by
+1.7e-2 (2.3e-2 at the worst sample) and dropping the Z_{k-1} term by 0.73;
+the field and spin-orbit terms, which a random block hides here (4e-4 and
+2e-7 of the result), are pinned by the term tests."""
 import numpy as np
 import pytest
 
@@ -73,7 +71,7 @@ def _sample(Y, nodes):
     return got.reshape(len(nodes), 2, len(COLS))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6), ("bf16", 5e-2)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 5e-6), ("bf16", 3e-2)])
 def test_filter_medium_sampled(medium_filter, prec, tol):
     m = medium_filter
     print(f"filter medium {prec}", flush=True)
@@ -87,7 +85,7 @@ def test_filter_medium_sampled(medium_filter, prec, tol):
         err = np.abs(z - zref).max() / np.abs(zref).max()
         fro = np.linalg.norm(z - zref) / np.linalg.norm(zref)
         print(f"  Z-part max rel err {err:.3e}, over all samples {fro:.3e}")
-        assert 1e-5 < fro < 3e-2, fro
+        assert 1e-5 < fro < 1.5e-2, fro
         assert err < tol, err
         return
     err = np.abs(got - m["ref"]).max() / np.abs(m["ref"]).max()
