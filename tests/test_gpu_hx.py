@@ -71,6 +71,37 @@ def test_hx_ragged_columns(B, tiny):
     assert _rel(Y1, ref[:, :1]) < 1e-12
 
 
+def test_block_argument_errors(B, tiny):
+    """Blocks the C ABI rejects before any device work, with CHFSI_E_ARG: no
+    columns, more columns than the context was planned for, a leading
+    dimension below the column count, an unknown precision, Y the same
+    block as X, a filter degree of 0 or above 256, and a filter output that
+    overlaps R.  The output block is left untouched."""
+    p, o = tiny
+    op = B.Chfsi(p, max_nvec=8)
+    X = _dev(synth.random_block(p.ndof, 8, 105))
+    Y = _dev(np.full((p.ndof, 8), 7.0 + 3.0j))
+    L, ctx, s = op.L, op.ctx, B._stream()
+
+    def code(rc):
+        assert rc == B.E_ARG, (rc, L.chfsi_last_error(ctx))
+
+    code(L.chfsi_apply_H(ctx, 0, B._ptr(X), B._ptr(Y), 0, 8, s))
+    code(L.chfsi_apply_H(ctx, 0, B._ptr(X), B._ptr(Y), 9, 9, s))
+    code(L.chfsi_apply_H(ctx, 0, B._ptr(X), B._ptr(Y), 8, 4, s))
+    code(L.chfsi_apply_H(ctx, 7, B._ptr(X), B._ptr(Y), 8, 8, s))
+    code(L.chfsi_apply_M(ctx, B._ptr(X), B._ptr(Y), 0, 8, s))
+    code(L.chfsi_apply_H(ctx, 0, B._ptr(X), B._ptr(X), 8, 8, s))
+    ritz = torch.linspace(-1.0, 1.0, 8, dtype=torch.float64, device="cuda")
+    b = (B.C.c_double * 3)(-1.0, 2.0, 50.0)
+    R = _dev(synth.random_block(p.ndof, 8, 106))
+    for deg in (0, 257):
+        code(L.chfsi_filter(ctx, 0, deg, b, B._ptr(X), B._ptr(ritz), B._ptr(R), B._ptr(Y), 8, 8, s))
+    code(L.chfsi_filter(ctx, 0, 3, b, B._ptr(X), B._ptr(ritz), B._ptr(R), B._ptr(R), 8, 8, s))
+    torch.cuda.synchronize()
+    assert torch.all(Y == 7.0 + 3.0j)
+
+
 def test_hx_fp32_tiny(B, tiny):
     p, o = tiny
     X = synth.random_block(p.ndof, 32, 104)
