@@ -222,8 +222,9 @@ def slab_leg(nvec=256, degree=40, reps=3, precs=("fp64", "fp32", "bf16"), filter
     8,429,568 nodes, 256 atoms x 8 projectors), one block of nvec vectors:
     H X in FP64, FP32 and bfloat16 with the cell kernel's roofline, and the
     degree-40 filter pass over one block of wavefunctions in bfloat16
-    (nvec columns) and FP64 (nvec/2 columns, the widest FP64 block beside
-    the other buffers in 288 GB) on synthetic X, R and Ritz values."""
+    (nvec columns), FP32 and FP64 (nvec/2 columns; half is the widest FP64
+    block beside the other buffers in 288 GB) on synthetic X, R and Ritz
+    values."""
     import numpy as np
     import torch
 
@@ -262,7 +263,7 @@ def slab_leg(nvec=256, degree=40, reps=3, precs=("fp64", "fp32", "bf16"), filter
     ritz = torch.linspace(-1.0, 2.0, nvec, dtype=torch.float64)
     bounds = [-1.0, 2.0, lmax]
     filt = {}
-    for prec, ncol in (("bf16", nvec), ("fp64", nvec // 2)):
+    for prec, ncol in (("bf16", nvec), ("fp32", nvec // 2), ("fp64", nvec // 2)):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record()
         op.filter(Xf, ritz, R, degree, bounds, prec=prec, Y=Xf, nvec=ncol)
@@ -274,6 +275,7 @@ def slab_leg(nvec=256, degree=40, reps=3, precs=("fp64", "fp32", "bf16"), filter
         log(f"[bench] slab filter {prec}: degree {degree}, {ncol} columns in {sec:.2f} s "
             f"({filt[prec]['hx_gdofvec_per_s']:.2f} GDoF*vec/s of H X)")
     filt["bf16_speedup_per_column"] = filt["fp64"]["sec_per_column"] / filt["bf16"]["sec_per_column"]
+    filt["fp32_speedup_per_column"] = filt["fp64"]["sec_per_column"] / filt["fp32"]["sec_per_column"]
     filt["lambda_max"] = lmax
     out["filter_degree40"] = filt
     del Xf, R, op
