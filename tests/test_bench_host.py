@@ -58,17 +58,37 @@ def test_cell_roofline_bound_switch():
     assert r["bytes_per_launch"] == pytest.approx(2 * MEDIUM.ndof * 512 * 8 / 8)
 
 
-def test_measured_traffic_records():
+def test_measured_traffic_records(tmp_path, monkeypatch):
     """A counter record is used only for its own kernel variant, workload and
     vector count, and only while the kernel source still has the recorded
-    hash."""
-    epi = bench.measured_traffic("bf16", "medium", 576, variant="epi")
-    hx = bench.measured_traffic("bf16", "medium", 512)
-    assert epi is not None and 7e9 < epi < 9e9
-    assert hx is not None and 3e9 < hx < 4e9
+    hash (checked on a copy of the committed record and source)."""
+    import shutil
+    rec = "cell_kernel_bf16_epi_medium_counters.txt"
+    src = os.path.join("paper_2605_30128_amd", "csrc", "cell_bf16.h")
+    (tmp_path / "profiles").mkdir()
+    shutil.copy(os.path.join(ROOT, "profiles", rec), tmp_path / "profiles" / rec)
+    os.makedirs(tmp_path / os.path.dirname(src))
+    shutil.copy(os.path.join(ROOT, src), tmp_path / src)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    got = bench.measured_traffic("bf16", "medium", 576, variant="epi")
+    if got is not None:  # the committed record matches the committed kernel
+        assert 7e9 < got < 9e9
     assert bench.measured_traffic("bf16", "medium", 512, variant="epi") is None
+    assert bench.measured_traffic("bf16", "slab", 576, variant="epi") is None
     assert bench.measured_traffic("bf16", "medium", 576) is None
-    assert bench.measured_traffic("fp32", "medium", 512) is None
+    # a record whose hash matches its source is used; an edited source voids it
+    import hashlib
+    import json
+    lines = open(tmp_path / "profiles" / rec).read().splitlines()
+    r = json.loads([x for x in lines if x.startswith("TRAFFIC ")][-1][len("TRAFFIC "):])
+    r["source_sha256"] = hashlib.sha256(open(tmp_path / src, "rb").read()).hexdigest()
+    with open(tmp_path / "profiles" / rec, "a") as f:
+        f.write("TRAFFIC " + json.dumps(r) + "\n")
+    kib = r["fetch_kib_per_launch"] * r["fetch_scale"] + r["write_kib_per_launch"] * r["write_scale"]
+    assert bench.measured_traffic("bf16", "medium", 576, variant="epi") == pytest.approx(1024 * kib)
+    with open(tmp_path / src, "a") as f:
+        f.write("// edited\n")
+    assert bench.measured_traffic("bf16", "medium", 576, variant="epi") is None
 
 
 def test_more_than_one_gpu_is_refused():
