@@ -283,6 +283,41 @@ def slab_leg(nvec=256, degree=40, reps=3, precs=("fp64", "fp32", "bf16"), filter
     return out
 
 
+def adjoint_leg(op, p, nvec, reps=3):
+    """The field adjoint of H X (dV, dB at the quadrature points for a pair
+    X, G of nvec columns) in FP64 and FP32 with device events: its work per
+    cell and vector is the two interpolations Phi X and Phi G on four real
+    columns (16 n^2 flops) and the four spin sums per quadrature point (32 n);
+    its bytes are reading X and G once."""
+    import numpy as np
+    import torch
+
+    from paper_2605_30128_amd import synth
+    n = (p.degree + 1) ** 3
+    flops = p.ncells * nvec * (16 * n * n + 32 * n)
+    out = {}
+    for prec, dt in (("fp64", torch.complex128), ("fp32", torch.complex64)):
+        X = synth.device_block(p.ndof, nvec, 7301, dtype=dt)
+        G = synth.device_block(p.ndof, nvec, 7302, dtype=dt)
+        op.adjoint(X, G, prec=prec, want_dX=False)
+        ts = []
+        for _ in range(reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            op.adjoint(X, G, prec=prec, want_dX=False)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]) * 1e-3)
+        t = float(np.median(ts))
+        out[prec] = {"ms": t * 1e3, "tflops": flops / t / 1e12, "frac_mfma": flops / t / PEAK[prec],
+                     "bytes_hbm_frac": 2 * p.ndof * nvec * CSIZE[prec] / t / PEAK["hbm"]}
+        log(f"[bench] adjoint fields {prec}: {t * 1e3:.1f} ms, {flops / t / 1e12:.2f} TFLOP/s, "
+            f"{out[prec]['frac_mfma']:.3f} of the MFMA peak")
+        del X, G
+    torch.cuda.empty_cache()
+    return out
+
+
 def bfp_throughput(n=1 << 28, reps=5):
     """Device-event throughput of the block floating-point codec on n float
     values (1 GiB), per rate: bytes moved (floats and stream, read + write)
@@ -590,6 +625,8 @@ def main():
     ap.add_argument("--poisson-only", action="store_true", help="run only the Poisson leg")
     ap.add_argument("--no-pcg", action="store_true", help="Poisson leg: K x only")
     ap.add_argument("--kx-reps", type=int, default=50)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the field adjoint of H X in FP64 and FP32 (512 vectors)")
     ap.add_argument("--iter-only", action="store_true",
                     help="only the warm-up and timed R-ChFSI iterations (after the 1 GiB fill and sum that "
                          "calibrate the memory counters)")
@@ -643,6 +680,9 @@ def main():
     if args.hf:
         print(json.dumps({"hellmann_feynman": hellmann_feynman(op, p, cfg, prec=args.prec, tol=args.tol)}),
               flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(op, p, nhx)}), flush=True)
         return
     if args.converge:
         print(json.dumps({"convergence": converge(op, p, cfg, args.precs.split(","), args.tol, args.max_iter,
@@ -732,6 +772,7 @@ def main():
     pr = args.prec
     roof_hx = cell_roofline(p, pr, nhx, prof[pr]["ms_cell"], prof[pr]["launches"], args.config)
 
+    adj = adjoint_leg(op, p, nhx)
     bfp = bfp_throughput()
     log(f"[bench] bfp codec: " + ", ".join(f"{k} enc {v['encode_GBps']:.0f} / dec {v['decode_GBps']:.0f} GB/s"
                                            for k, v in bfp.items()))
@@ -788,6 +829,7 @@ def main():
         "hx_profile_ms": prof,
         "roofline": roof,
         "roofline_hx": roof_hx,
+        "adjoint": adj,
         "bfp_codec": bfp,
         "poisson": poi,
         "cpu_baseline": cpu,

@@ -664,7 +664,7 @@ struct AdjParams {
 };
 
 template <typename T, int MT, int NP>
-__global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams a) {
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 && NP <= 352 ? 2 : 1) void adjoint_kernel(AdjParams a) {
     using acc_t = typename MM<T>::acc;
     constexpr int VB = 4 * MT, CB = 16 * MT;
     constexpr int XS = CB + LdsPad<T>::v;
@@ -690,11 +690,11 @@ __global__ __launch_bounds__(kThreads) void adjoint_kernel(AdjParams a) {
         acc_t tx[NTW], tg[NTW];
 #pragma unroll
         for (int t = 0; t < NTW; ++t) { tx[t] = acc_t{0, 0, 0, 0}; tg[t] = acc_t{0, 0, 0, 0}; }
-        mfma_panel<T, NTW, NP, XS, false>(tx, xs, BphiT, m, nt0, lane);
+        mfma_panel<T, NTW, NP, XS, (NP <= 352)>(tx, xs, BphiT, m, nt0, lane);
         __syncthreads();
         gather_block<T, VB, NP, XS>(xs, grow, nullptr, a.G, a.ld, a.nvec, vb * VB, a.n);
         __syncthreads();
-        mfma_panel<T, NTW, NP, XS, false>(tg, xs, BphiT, m, nt0, lane);
+        mfma_panel<T, NTW, NP, XS, (NP <= 352)>(tg, xs, BphiT, m, nt0, lane);
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
             double xur = tx[t][0], xui = tx[t][1], xdr = tx[t][2], xdi = tx[t][3];
@@ -983,7 +983,7 @@ hipError_t launch_adjoint_fields(const chfsi_ctx *c, chfsi_prec prec, const void
     if (prec == CHFSI_FP64) {
         CHFSI_DISPATCH_NP(c->m.npad, return (run_adjoint<double, 2, NP>(c, X, G, nvec, ld, dV, dB, s)));
     }
-    CHFSI_DISPATCH_NP(c->m.npad, return (run_adjoint<float, 4, NP>(c, X, G, nvec, ld, dV, dB, s)));
+    CHFSI_DISPATCH_NP(c->m.npad, return (run_adjoint<float, 2, NP>(c, X, G, nvec, ld, dV, dB, s)));
 }
 
 hipError_t launch_setup_fields(const chfsi_ctx *c, const double *V, const double *B, hipStream_t s) {
