@@ -165,16 +165,19 @@ __device__ __forceinline__ void mfma_panel(typename MM<T>::acc *acc, const T *as
 // completion the LDS counter also waits for); never written.
 __device__ double kZeroPiece[4] = {0.0, 0.0, 0.0, 0.0};
 
+// threads of a cell-kernel workgroup: MT row tiles x two column groups of waves
+constexpr int cell_threads(int mt) { return 128 * mt; }
+
 // One workgroup per (cell, VB = 4 MT vectors): its waves split the 16 MT
 // rows x NP columns of the block MT (16-row tiles) x WN (column groups of
 // NTW 16-column tiles).
 template <typename T, int MT, int NP>
-__global__ __launch_bounds__(kCellThreads, sizeof(T) == 4 && NP <= 352 ? 2 : 1) void cell_kernel(CellParams a, EpiArgs ep) {
+__global__ __launch_bounds__(cell_threads(MT), MT == 1 || (sizeof(T) == 4 && NP <= 352) ? 2 : 1) void cell_kernel(CellParams a, EpiArgs ep) {
     using TC = typename Cplx<T>::type;
     using acc_t = typename MM<T>::acc;
     constexpr int CB = 16 * MT, VB = 4 * MT;
     constexpr int XS = CB + LdsPad<T>::v;
-    constexpr int NT = NP / 16, WN = kCellThreads / 64 / MT, NTW = NT / WN;
+    constexpr int NT = NP / 16, WN = cell_threads(MT) / 64 / MT, NTW = NT / WN;
     static_assert(NT % WN == 0, "column tiles split evenly over the wave groups");
     __shared__ __attribute__((aligned(16))) T xs[NP * XS];
     __shared__ int ijk[NP], grow[NP];
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(kCellThreads, sizeof(T) == 4 && NP <= 352 ? 2 : 1) 
     cell_tables<T>(ijk, grow, gsc, scaled ? reinterpret_cast<const T *>(a.dinv) : nullptr, NP, a.n, a.n1, ex, ey,
                    ez, a.p, a.Nx, a.Ny, a.Nz);
     __syncthreads();
-    gather_block<T, VB, NP, XS, kCellThreads>(xs, grow, scaled ? gsc : nullptr, a.X, a.ld, a.nvec, vb * VB, a.n);
+    gather_block<T, VB, NP, XS, cell_threads(MT)>(xs, grow, scaled ? gsc : nullptr, a.X, a.ld, a.nvec, vb * VB, a.n);
     __syncthreads();
 
     acc_t y[NTW];
@@ -877,7 +880,7 @@ static hipError_t run_cell(const chfsi_ctx *c, int mode, int flags, double alpha
         a.cells = c->P<int>(L.colour_cells) + c->colour_ptr[col];
         a.ncl = ncl;
         a.px = col & 1; a.py = (col >> 1) & 1; a.pz = (col >> 2) & 1;
-        hipLaunchKernelGGL((cell_kernel<T, MT, NP>), dim3((unsigned)(ncl * nvb)), dim3(kCellThreads), 0, s, a, ep);
+        hipLaunchKernelGGL((cell_kernel<T, MT, NP>), dim3((unsigned)(ncl * nvb)), dim3(cell_threads(MT)), 0, s, a, ep);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -958,8 +961,12 @@ static hipError_t run_adjoint(const chfsi_ctx *c, const void *X, const void *G, 
 hipError_t launch_cell_op(const chfsi_ctx *c, chfsi_prec prec, int mode, int flags, double alpha,
                           const void *X, void *Y, int64_t nvec, int64_t ld, hipStream_t s, const EpiArgs *epi) {
     if (prec == CHFSI_FP64) {
-        CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, 2, NP>(c, mode, flags, alpha, X, Y, nvec, ld, s,
-                                                                      epi)));
+        // double: up to p = 6, 4 vectors per workgroup (62 KB of LDS at p = 6),
+        // two workgroups per CU, one's gather and assembly beside the other's
+        // MFMAs (146.7 against 149.8 ms per H X with 8 vectors and one
+        // workgroup per CU); at p = 7 the 8-vector block
+        CHFSI_DISPATCH_NP(c->m.npad, return (run_cell<double, NP <= 352 ? 1 : 2, NP>(c, mode, flags, alpha, X, Y,
+                                                                                     nvec, ld, s, epi)));
     }
     if (prec == CHFSI_BF16) return launch_cell_op_bf16(c, mode, flags, alpha, X, Y, nvec, ld, s, epi);
     // float: 8 vectors per workgroup (two column groups of tiles per row

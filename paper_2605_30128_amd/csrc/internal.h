@@ -13,7 +13,6 @@
 namespace chfsi {
 
 constexpr int kThreads = 256;       // threads per workgroup of the projection and adjoint kernels
-constexpr int kCellThreads = 256;   // threads per workgroup of the FP64/FP32 cell-operator kernel
 constexpr int kMaxN = 512;          // nodes per cell (p <= 7)
 constexpr int kMaxBeta = 16;
 constexpr int kMaxDegree = 256;     // Chebyshev degree limit (Lambda_k table)
